@@ -1,0 +1,172 @@
+"""Benchmark: transposed nonzeros per second on one MI355X.
+
+Workload (one step): the 3-mode tensor with extents 500000 x 20000 x 2000000, 1e8 distinct
+nonzeros whose coordinates are Zipf(1.1) over a relabelled extent, int32 coordinates, fp64
+values, input order (0,1,2), transposed to all five other orders.  Inputs are resident in
+device memory before the timed region; value = 5e8 * steps / seconds.
+
+Also reported: the roofline of the dominant kernel (the digit pass), timed with HIP events
+recorded by the library on the stream each launch runs on, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "transposed nnz/s & HBM GB/s (% of peak); learned+batched vs plain schedule"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_digit_plain_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2005_10427_amd", "csrc", "kernels.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per digit-pass launch from rocprofv3 counters, if taken on this kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha256") != kernel_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(T, sigmas, budget_s=20.0):
+    """The oracle (numpy stable sort + gather), single-threaded, on a prefix sample of the
+    tensor (still sorted in the input order), all requested orders."""
+    import numpy as np
+    from oracle.transpose import transpose as oracle_transpose
+    n = 1_000_000
+    t_one = None
+    while True:
+        crd = [c[:n] for c in T.crd]
+        val = T.val[:n]
+        t0 = time.perf_counter()
+        for s in sigmas:
+            oracle_transpose(crd, val, s)
+        dt = time.perf_counter() - t0
+        if dt > budget_s / 4 or n * 4 > T.nnz:
+            t_one = dt
+            break
+        n *= 4
+    rate = n * len(sigmas) / t_one
+    return {"value": rate, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} nonzeros of the workload tensor, all {len(sigmas)} orders, "
+                      f"{t_one:.1f} s single-threaded numpy (lexsort + gather)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sched", default="minimal", choices=["minimal", "top2", "lsd", "auto"])
+    ap.add_argument("--nnz", type=int, default=None, help="shrink the workload (testing only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU path is "
+              f"not built", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from datagen import CONFIGS, config_tensor
+    from paper_2005_10427_amd import qsd
+
+    qsd.load()
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    cfg = CONFIGS["plain"]
+    sigmas = cfg["sigmas"]
+    log("generating workload ...")
+    t0 = time.time()
+    T = config_tensor("plain", nnz=args.nnz)
+    N = T.nnz
+    log(f"generated {N} nonzeros in {time.time() - t0:.1f} s")
+
+    dev = torch.device("cuda:0")
+    crd = [torch.from_numpy(c).to(dev) for c in T.crd]
+    val = torch.from_numpy(T.val).to(dev)
+    plans = [qsd.Plan(T.extents, T.in_order, s, N, "int32", "float64", args.sched) for s in sigmas]
+    ws = torch.empty(max(p.ws_bytes for p in plans), dtype=torch.uint8, device=dev)
+    outs = [([torch.empty_like(c) for c in crd], torch.empty_like(val)) for _ in sigmas]
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        for p, (oc, ov) in zip(plans, outs):
+            p.transpose(crd, val, oc, ov, stream=stream, ws=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    status = qsd.qsd_device_status(ws.data_ptr(), stream.cuda_stream)
+    if status:
+        log(f"device status {status}")
+        return 1
+    log("warm-up done; timing")
+
+    qsd.qsd_profile_start()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = qsd.qsd_profile_stop()
+    sec = t1 - t0
+    ms_per_step = 1e3 * sec / args.steps
+    value = N * len(sigmas) * args.steps / sec
+    log(f"{ms_per_step:.3f} ms/step, {value / 1e9:.2f} G nnz/s")
+    for k, (n_l, ms, b) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        log(f"  {k:10s} launches={n_l:6d} total={ms:9.3f} ms avg={ms / max(n_l, 1) * 1e3:8.1f} us"
+            + (f"  {b / ms / 1e6:8.1f} GB/s" if b and ms else ""))
+
+    # roofline of the dominant kernel: algorithmic bytes per launch / mean launch time
+    n_l, ms, b = prof["digit"]
+    avg_s = ms / n_l / 1e3
+    bytes_per_launch = b / n_l
+    achieved = bytes_per_launch / avg_s / 1e9
+    traffic = measured_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_digit (global digit pass)", "launches": n_l,
+                "avg_launch_us": round(avg_s * 1e6, 2),
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+    whole_bytes = sum(v[2] for v in prof.values())
+    out = {
+        "metric": METRIC, "value": value, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "plain: 3-mode COO 500000x20000x2000000, 1e8 distinct nonzeros, "
+                               "Zipf(1.1) coordinates, int32 coordinates, fp64 values, input order "
+                               "(0,1,2) -> all 5 other orders per step",
+                   "nnz": N, "orders": [list(s) for s in sigmas], "schedule": args.sched},
+        "roofline": roofline,
+        "modelled_bytes_per_step": whole_bytes / args.steps,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample ...")
+        out["cpu_baseline"] = cpu_baseline(T, sigmas)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,153 @@
+/*
+ * qsd.h -- C ABI of libqsd: sparse-tensor transposition on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Mueller et al., "Sparse Tensor Transpositions", Sec. 2.2): a tensor in
+ * coordinate (COO) format is stored as N nonzeros listed in the lexicographic order of a
+ * complete mode order `in_order` (the paper's tau, most significant mode first, Sec. 2).
+ * Transposing it to `out_order` (sigma) lists the same nonzeros in sigma's lexicographic
+ * order.  Nonzeros whose coordinates tie keep their input order (the paper's partial sorts
+ * are stable, Sec. 3.1), so the result is unique and reproducible bit for bit.
+ *
+ * Layout: structure of arrays.  Coordinates are r separate device arrays, one per mode,
+ * indexed by the ORIGINAL mode number (crd[m][j] is mode m of nonzero j), of int32 or
+ * int64; values are one device array of fp32 or fp64 moved as raw bits (no arithmetic:
+ * signed zeros and NaN payloads survive).  Coordinates are 0-based: 0 <= crd[m][j] < n_m.
+ *
+ * Ownership: the caller owns every device buffer (inputs, outputs, workspace).  The library
+ * allocates no device memory in qsd_transpose / qsd_pack_csf / qsd_batch_transpose; it
+ * only launches kernels on the caller's stream, without host synchronisation (except when
+ * QSD_VALIDATE is set), so these calls may be captured into a HIP graph.
+ *
+ * Errors: argument errors are returned synchronously before anything is launched.
+ * A failed HIP launch returns QSD_ERR_HIP.  Plans and batches are immutable after
+ * creation and may be used from several streams if each call has its own workspace.
+ */
+#ifndef QSD_H
+#define QSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QSD_MAX_ORDER 8              /* modes per tensor */
+#define QSD_MAX_NNZ ((int64_t)1 << 30) /* nnz must be below this */
+
+typedef enum qsd_status {
+    QSD_OK = 0,
+    QSD_ERR_NULL = 1,          /* a required pointer is NULL */
+    QSD_ERR_BAD_ORDER = 2,     /* an order is not a permutation of 0..r-1, or r out of range */
+    QSD_ERR_BAD_EXTENT = 3,    /* an extent is < 1 or does not fit the coordinate type */
+    QSD_ERR_TOO_LARGE = 4,     /* nnz < 0, nnz >= QSD_MAX_NNZ, or nnz above the planned nnz */
+    QSD_ERR_UNSORTED = 5,      /* QSD_VALIDATE: input not sorted under in_order */
+    QSD_ERR_COORD_RANGE = 6,   /* QSD_VALIDATE: a coordinate outside [0, n_m) */
+    QSD_ERR_WORKSPACE = 7,     /* workspace NULL or smaller than the plan requires */
+    QSD_ERR_UNSUPPORTED = 8,   /* combination not supported (e.g. bad type enum) */
+    QSD_ERR_HIP = 9,           /* a HIP runtime call or kernel launch failed */
+    QSD_ERR_DEVICE = 10        /* a kernel reported an internal failure (see qsd_device_status) */
+} qsd_status;
+
+typedef enum qsd_index_t { QSD_I32 = 0, QSD_I64 = 1 } qsd_index_t;
+typedef enum qsd_value_t { QSD_F32 = 0, QSD_F64 = 1 } qsd_value_t;
+
+/* Pass schedules; every schedule produces the identical output.
+ * MINIMAL: QuesadillaSort (Alg. 3, Sec. 3.5) -- the provably minimal number of partial
+ *          sorts, bucketed ones only where necessary (Thm 3.4, Thm 3.5).
+ * TOP2:    Top-K-sadilla (Sec. 3.6) with K = min(2, r-2): MINIMAL towards
+ *          (sigma_1..sigma_K, remaining modes in input order), then every bucket of equal
+ *          (sigma_1..sigma_K) sorted completely.
+ * LSD:     full least-significant-digit radix sort over all r modes (the paper's "radix").
+ * AUTO:    a learned cost model picks one of the three (MINIMAL when no model is loaded). */
+typedef enum qsd_sched_t {
+    QSD_SCHED_AUTO = 0,
+    QSD_SCHED_MINIMAL = 1,
+    QSD_SCHED_TOP2 = 2,
+    QSD_SCHED_LSD = 3
+} qsd_sched_t;
+
+#define QSD_VALIDATE 1u   /* qsd_transpose checks ranges and input order first (synchronises) */
+
+typedef struct qsd_desc {
+    int32_t order;              /* r, 1..QSD_MAX_ORDER */
+    int64_t nnz;                /* largest nnz the plan will be used with */
+    const int64_t* extents;     /* host, r entries n_m >= 1 */
+    qsd_index_t crd_type;
+    qsd_value_t val_type;
+    const int32_t* in_order;    /* host, r entries, permutation of 0..r-1 (tau) */
+    const int32_t* out_order;   /* host, r entries, permutation of 0..r-1 (sigma) */
+    uint32_t flags;             /* QSD_VALIDATE */
+} qsd_desc;
+
+typedef struct qsd_plan_s* qsd_plan_t;
+
+/* Build a plan on the host (Alg. 3 and its variants; digit splitting).  All inputs are
+ * copied.  *out receives a plan to release with qsd_plan_destroy. */
+qsd_status qsd_plan(const qsd_desc* desc, qsd_sched_t sched, qsd_plan_t* out);
+void qsd_plan_destroy(qsd_plan_t plan);
+
+/* Bytes of device workspace qsd_transpose needs for this plan (its planned nnz). */
+qsd_status qsd_plan_workspace(qsd_plan_t plan, size_t* bytes);
+
+/* Human-readable plan (schedule, PartialSort calls, groups, digit passes) into buf
+ * (NUL-terminated, truncated to len).  Format, one item per line:
+ *   sched=<MINIMAL|TOP2|LSD> K=<k>
+ *   call prefix=<modes comma-separated or empty> mode=<m>      (QuesadillaSort calls)
+ *   group prefix=<...> keys=<modes, most significant first> bits=<b> passes=<d>
+ */
+qsd_status qsd_plan_describe(qsd_plan_t plan, char* buf, size_t len);
+
+/* Transpose.  in_crd / out_crd: host arrays of r DEVICE pointers (mode order);
+ * in_val / out_val: device pointers.  nnz <= planned nnz.  Inputs are read only; outputs
+ * must not overlap the inputs or the workspace.  ws: device workspace of ws_bytes >=
+ * qsd_plan_workspace.  Asynchronous on `stream`. */
+qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz,
+                         const void* const* in_crd, const void* in_val,
+                         void* const* out_crd, void* out_val,
+                         void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Compressed sparse fiber (CSF) pack of a tensor already sorted under the plan's out_order
+ * (e.g. qsd_transpose's output).  Levels d = 1..r store mode sigma_d.  Every level is
+ * compressed: level d has F_d fibers (maximal runs sharing sigma_1..sigma_d; at d = r
+ * every nonzero is its own leaf, F_r = nnz).
+ *   crd[d-1]: device array (crd type) with room for nnz entries; receives F_d coordinates.
+ *   pos[d-1]: device array (int32 for QSD_I32 plans, int64 for QSD_I64) with room for
+ *             nnz + 1 entries (2 for d = 1); receives F_{d-1} + 1 offsets: the children of
+ *             level-(d-1) fiber p are level-d fibers pos[d-1][p] .. pos[d-1][p+1]-1.
+ *   fiber_counts: device int64[r + 1] receiving F_0 = 1, F_1, ..., F_r.
+ * ws: device workspace of qsd_csf_workspace bytes. */
+qsd_status qsd_csf_workspace(qsd_plan_t plan, size_t* bytes);
+qsd_status qsd_pack_csf(qsd_plan_t plan, int64_t nnz, const void* const* sorted_crd,
+                        void* const* pos, void* const* crd, int64_t* fiber_counts,
+                        void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Device-side status of the last call that used this workspace: 0 when every kernel ran
+ * normally, otherwise a bit set (1: a bounded wait in a scan timed out).  Synchronises
+ * `stream` and reads 4 bytes.  Validation results are returned by qsd_transpose itself. */
+qsd_status qsd_device_status(void* ws, hipStream_t stream, uint32_t* code);
+
+const char* qsd_status_str(qsd_status s);
+
+/* Kernel timing.  Between qsd_profile_start and qsd_profile_stop every kernel the library
+ * launches (from any thread, on any stream) is bracketed by two hipEvents recorded on the
+ * stream it is launched on.  qsd_profile_stop synchronises those events and returns one
+ * entry per kernel kind: launches, summed event durations, and the algorithmic bytes the
+ * launches had to move (the data-movement model of the kind; 0 where none is modelled).
+ * Kinds: zero, copy, validate, hist, digit, boundary, classify, small, hist_seg,
+ * digit_seg, csf.  Recording adds two event records per launch; it is off by default. */
+typedef struct qsd_kernel_stat {
+    char name[24];
+    int64_t launches;
+    double total_ms;
+    double bytes;
+} qsd_kernel_stat;
+qsd_status qsd_profile_start(void);
+qsd_status qsd_profile_stop(qsd_kernel_stat* out, int32_t max, int32_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSD_H */

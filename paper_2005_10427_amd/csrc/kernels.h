@@ -1,0 +1,166 @@
+// Kernel argument blocks and launchers (host side).  All positions are 32-bit: nnz is
+// limited to QSD_MAX_NNZ = 2^30 so that a scan status word can hold a 30-bit count.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace qsd {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kBins = 256;         // 8-bit digits: one bin per thread
+constexpr int kSmallCap = 4096;    // records one workgroup sorts in LDS
+constexpr int kTinyLen = 2048;     // segments up to this length are packed by region
+constexpr int kRegion = 2048;      // region width for packing tiny segments
+constexpr int kBoundTile = 4096;   // elements per tile of the boundary scan
+constexpr int kCtlWords = 1024;    // control block (counters, sizes, flags), 4 KB
+
+// control block word offsets (uint32 unless noted)
+enum CtlSlot {
+    kCtlErr = 0,        // device status bits
+    kCtlValid = 1,      // validation result bits
+    kCtlNb = 2,         // number of segments
+    kCtlNMed = 3,       // medium segments
+    kCtlLarge = 4,      // uint64 at words 4-5: (large segments << 32) | large tiles
+    kCtlBoundCnt = 8,   // tile counter of the boundary scan
+    kCtlPassCnt = 16,   // 256 tile counters, one per digit pass launch
+};
+
+struct DevKey {
+    uint64_t mask[8];
+    int32_t src_lo[8];
+    int32_t dst[8];
+};
+
+struct SegRec {
+    uint32_t start, len, tile_base, pad;
+};
+
+// Items per thread of the digit pass for a record of r coordinates: keeps the per-thread
+// record registers within budget.
+inline int digit_items(int r, int crd_bytes, int val_bytes) {
+    const int words = r * (crd_bytes / 4) + val_bytes / 4;
+    return words <= 6 ? 16 : 8;
+}
+inline int digit_tile(int r, int crd_bytes, int val_bytes) {
+    return kBlock * digit_items(r, crd_bytes, val_bytes);
+}
+
+struct DigitArgs {
+    const void* src_crd[8];
+    const void* src_val;
+    void* dst_crd[8];
+    void* dst_val;
+    DevKey key;
+    int32_t lo, bits;           // digit = (key >> lo) & ((1 << bits) - 1)
+    uint32_t n;                 // global mode: number of records
+    uint32_t ntiles;            // global mode: tiles; segment mode: upper bound (grid sizing)
+    int32_t seg_mode;           // 0: one segment [0, n); 1: the large-segment list
+    uint32_t hist_stride;       // segment mode: words between two segments' histograms
+    const uint32_t* hist;       // this pass's digit histogram (segment mode: of segment 0)
+    uint32_t* status;           // look-back words of this pass, kBins per tile
+    uint32_t* status_next;      // zeroed for the next pass (may be null)
+    uint32_t* tile_counter;
+    const uint64_t* large_ctl;  // segment mode
+    const SegRec* large;        // segment mode
+    uint32_t* err;
+};
+
+struct HistArgs {
+    const void* crd[8];
+    DevKey key;
+    int32_t npass;
+    int32_t lo[16];
+    int32_t bits[16];
+    uint32_t n;                 // global mode
+    int32_t seg_mode;
+    uint32_t tile;              // segment mode: records per tile
+    uint32_t* hist;             // global: npass*kBins; segment: per large segment
+    uint32_t hist_stride;
+    uint32_t* status_zero;      // status words of the first pass, zeroed here
+    uint32_t status_words;      // global mode: words to zero
+    const uint64_t* large_ctl;
+    const SegRec* large;
+};
+
+struct BoundArgs {
+    const void* crd[8];
+    int32_t nprefix;
+    int32_t prefix[8];
+    uint32_t n;
+    uint32_t* seg_start;        // nb + 1 entries written (seg_start[nb] = n)
+    uint32_t* status;           // one word per tile, zeroed beforehand
+    uint32_t* tile_counter;
+    uint32_t* nb_out;
+    uint32_t* err;
+};
+
+struct ClassArgs {
+    const uint32_t* seg_start;
+    const uint32_t* nb;
+    uint32_t tile;              // digit-pass tile of the large path
+    uint32_t* nmed;
+    uint2* med;
+    uint64_t* large_ctl;
+    SegRec* large;
+    uint32_t* seg_hist;         // zeroed per large segment
+    uint32_t hist_stride;
+};
+
+struct SmallArgs {
+    const void* src_crd[8];
+    const void* src_val;
+    void* dst_crd[8];
+    void* dst_val;
+    int32_t r;
+    DevKey key;                 // whole group key (<= 52 bits)
+    int32_t key_bits;
+    uint32_t n;
+    uint32_t nregions;
+    const uint32_t* seg_start;
+    const uint32_t* nb;
+    const uint32_t* nmed;
+    const uint2* med;
+};
+
+struct ZeroArgs {
+    uint32_t* ptr[4];
+    uint64_t words[4];
+};
+
+struct ValidateArgs {
+    const void* crd[8];
+    int32_t r;
+    int64_t ext[8];
+    int32_t in_order[8];
+    uint32_t n;
+    uint32_t* flags;            // bit 0: out of range, bit 1: unsorted
+};
+
+struct CsfArgs {
+    const void* crd[8];         // sorted coordinates, original mode order
+    int32_t r;
+    int32_t sigma[8];
+    uint32_t n;
+    void* pos[8];
+    void* out_crd[8];
+    int64_t* fiber_counts;
+    uint32_t* status;           // (r-1) words per tile, zeroed beforehand
+    uint32_t* tile_counter;
+    uint32_t* err;
+};
+
+hipError_t launch_zero(const ZeroArgs& a, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
+hipError_t launch_hist(const HistArgs& a, int r, int crd_bytes, int grid, hipStream_t s);
+hipError_t launch_digit(const DigitArgs& a, int r, int crd_bytes, int val_bytes, hipStream_t s);
+hipError_t launch_boundary(const BoundArgs& a, int crd_bytes, hipStream_t s);
+hipError_t launch_classify(const ClassArgs& a, uint32_t max_segments, hipStream_t s);
+hipError_t launch_small(const SmallArgs& a, int crd_bytes, int val_bytes, uint32_t max_items,
+                        hipStream_t s);
+hipError_t launch_validate(const ValidateArgs& a, int crd_bytes, hipStream_t s);
+hipError_t launch_csf(const CsfArgs& a, int crd_bytes, hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace qsd

@@ -1,0 +1,968 @@
+// HIP kernels for gfx950 (CDNA4, wave64).
+//
+// The digit pass is a stable counting-sort pass (Alg. 1: count, prefix sum, move in input
+// order) made single-pass on the GPU:
+//   * the global count of every digit comes from an upfront histogram kernel (the count
+//     loop, done once for all digit passes of a key since counts do not depend on order);
+//   * each workgroup ranks a tile of records by digit with wave64 ballots (stable within the
+//     tile), publishes its per-digit counts and reads its predecessors' counts with a
+//     decoupled look-back (Merrill & Garland, 2016) -- the "private count arrays merged in
+//     order" of Sec. 3.1, merged in (digit-major, tile-minor) order;
+//   * the tile is reordered through LDS so that every digit's run is written contiguously,
+//     and whole records (all coordinates and the value bits) move, so no final gather runs.
+// Bucketed groups (Alg. 2) are sorted segment by segment (the paper's decomposition along
+// bucket boundaries, Sec. 3.2): short segments entirely in LDS, long ones by the same digit
+// pass restricted to each segment.
+#include "kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+namespace qsd {
+namespace {
+
+constexpr uint32_t kFlagA = 1u << 30;  // aggregate of this tile only
+constexpr uint32_t kFlagP = 2u << 30;  // inclusive prefix up to this tile
+constexpr uint32_t kCntMask = (1u << 30) - 1;
+constexpr uint32_t kSpinLimit = 1u << 20;
+constexpr int kWaves = kBlock / 64;
+
+__device__ __forceinline__ uint32_t ld_status(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_status(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+// number of set bits of m in lanes below this one
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread over the block; s_tmp holds kWaves words.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t inc = wave_incl_scan(v, lane);
+    if (lane == 63) s_tmp[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const uint32_t s = s_tmp[w];
+        before += (w < wave) ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    if (total) *total = tot;
+    return before + inc - v;
+}
+
+template <typename CT>
+__device__ __forceinline__ uint64_t compose_key(const CT (&c)[8], const DevKey& k, int r) {
+    uint64_t key = 0;
+    for (int m = 0; m < r; ++m)
+        if (k.mask[m]) key |= (((uint64_t)c[m] >> k.src_lo[m]) & k.mask[m]) << k.dst[m];
+    return key;
+}
+
+// ------------------------------------------------------------------------------ utility
+
+__global__ void __launch_bounds__(256) k_zero(ZeroArgs a) {
+    for (int r = 0; r < 4; ++r) {
+        uint32_t* p = a.ptr[r];
+        if (!p) continue;
+        for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < a.words[r]; i += gridDim.x * 256ull)
+            p[i] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                              uint64_t n16, const uint8_t* __restrict__ sb,
+                                              uint8_t* __restrict__ db, uint64_t bytes) {
+    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n16; i += gridDim.x * 256ull) dst[i] = src[i];
+    for (uint64_t i = n16 * 16 + blockIdx.x * 256ull + threadIdx.x; i < bytes; i += gridDim.x * 256ull)
+        db[i] = sb[i];
+}
+
+// ------------------------------------------------------------------------------ histograms
+
+// Counts of every digit of every pass of one key, over all records (global) or per large
+// segment.  Also clears the look-back words of the key's first digit pass.
+template <int R, typename CT>
+__global__ void __launch_bounds__(256) k_hist(HistArgs a) {
+    __shared__ uint32_t s_h[16 * kBins];
+    __shared__ uint32_t s_k;
+    const int tid = threadIdx.x;
+    const int words = a.npass * kBins;
+    for (int i = tid; i < words; i += kBlock) s_h[i] = 0;
+    const CT* src[8];
+#pragma unroll
+    for (int m = 0; m < R; ++m) src[m] = (const CT*)a.crd[m];
+
+    auto count = [&](uint32_t e) {
+        CT c[8];
+#pragma unroll
+        for (int m = 0; m < R; ++m) c[m] = a.key.mask[m] ? src[m][e] : CT(0);
+        const uint64_t key = compose_key<CT>(c, a.key, R);
+        for (int p = 0; p < a.npass; ++p) {
+            const uint32_t d = (uint32_t)(key >> a.lo[p]) & ((1u << a.bits[p]) - 1u);
+            atomicAdd(&s_h[p * kBins + d], 1u);
+        }
+    };
+    __syncthreads();
+    if (!a.seg_mode) {
+        for (uint32_t e = blockIdx.x * kBlock + tid; e < a.n; e += gridDim.x * kBlock) count(e);
+        __syncthreads();
+        for (int i = tid; i < words; i += kBlock) {
+            const uint32_t c = s_h[i];
+            if (c) atomicAdd(&a.hist[i], c);
+        }
+        for (uint64_t i = blockIdx.x * (uint64_t)kBlock + tid; i < a.status_words; i += gridDim.x * (uint64_t)kBlock)
+            a.status_zero[i] = 0;
+        return;
+    }
+    // segment mode: a static range of large-segment tiles per workgroup
+    const uint64_t lc = *a.large_ctl;
+    const uint32_t nL = (uint32_t)(lc >> 32), nT = (uint32_t)lc;
+    const uint32_t per = (nT + gridDim.x - 1) / gridDim.x;
+    const uint32_t t0 = blockIdx.x * per, t1 = min(nT, t0 + per);
+    int cur = -1;
+    for (uint32_t t = t0; t < t1; ++t) {
+        if (tid == 0) {
+            uint32_t lo = 0, hi = nL;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (a.large[mid].tile_base <= t) lo = mid; else hi = mid;
+            }
+            s_k = lo;
+        }
+        __syncthreads();
+        const int k = (int)s_k;
+        if (k != cur) {
+            if (cur >= 0) {
+                for (int i = tid; i < words; i += kBlock) {
+                    const uint32_t c = s_h[i];
+                    if (c) atomicAdd(&a.hist[(size_t)cur * a.hist_stride + i], c);
+                    s_h[i] = 0;
+                }
+            }
+            cur = k;
+        }
+        __syncthreads();
+        const SegRec s = a.large[k];
+        const uint32_t start = s.start + (t - s.tile_base) * a.tile;
+        const uint32_t end = min(s.start + s.len, start + a.tile);
+        for (uint32_t e = start + tid; e < end; e += kBlock) count(e);
+        a.status_zero[(size_t)t * kBins + tid] = 0;
+        __syncthreads();
+    }
+    if (cur >= 0) {
+        for (int i = tid; i < words; i += kBlock) {
+            const uint32_t c = s_h[i];
+            if (c) atomicAdd(&a.hist[(size_t)cur * a.hist_stride + i], c);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------ digit pass
+
+template <int R, typename CT, typename VT, int ITEMS, bool SEG>
+__global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
+    constexpr int TILE = kBlock * ITEMS;
+    __shared__ uint64_t s_x[TILE];               // record exchange (4- or 8-byte words)
+    __shared__ uint32_t s_cnt[kWaves * kBins];   // per-wave digit counters, then wave prefixes
+    __shared__ uint32_t s_tstart[kBins];         // first local slot of each digit
+    __shared__ uint32_t s_base[kBins];           // global slot of local slot 0 of each digit
+    __shared__ uint8_t s_dig[TILE];
+    __shared__ uint32_t s_tmp[2 * kWaves];
+    __shared__ uint32_t s_geo[5];                // tile id, start, len, segment base, k
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t dmask = (1u << a.bits) - 1u;
+
+    for (;;) {
+        if (tid == 0) {
+            const uint32_t t = atomicAdd(a.tile_counter, 1u);
+            uint32_t ntiles = a.ntiles, start = 0, len = 0, base = 0, k = 0;
+            if (SEG) {
+                const uint64_t lc = *a.large_ctl;
+                ntiles = (uint32_t)lc;
+                if (t < ntiles) {
+                    uint32_t lo = 0, hi = (uint32_t)(lc >> 32);
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (a.large[mid].tile_base <= t) lo = mid; else hi = mid;
+                    }
+                    const SegRec s = a.large[lo];
+                    k = lo;
+                    base = s.start;
+                    start = s.start + (t - s.tile_base) * TILE;
+                    len = min((uint32_t)TILE, s.start + s.len - start);
+                }
+            } else if (t < ntiles) {
+                start = t * TILE;
+                len = min((uint32_t)TILE, a.n - start);
+            }
+            s_geo[0] = (t < ntiles) ? t : 0xFFFFFFFFu;
+            s_geo[1] = start;
+            s_geo[2] = len;
+            s_geo[3] = base;
+            s_geo[4] = k;
+        }
+        __syncthreads();
+        const uint32_t t = s_geo[0];
+        if (t == 0xFFFFFFFFu) break;
+        const uint32_t start = s_geo[1], len = s_geo[2], seg_base = s_geo[3], k = s_geo[4];
+        const bool first = SEG ? (start == seg_base) : (t == 0);
+        const uint32_t* hist = a.hist + (size_t)k * a.hist_stride;
+
+        // ---- load whole records (wave w owns the contiguous slice [w*64*ITEMS, (w+1)*64*ITEMS))
+        CT c[R][ITEMS];
+        VT v[ITEMS];
+        uint32_t dg[ITEMS], lp[ITEMS];
+        const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t off = wb + i * 64;
+            const bool ok = off < len;
+#pragma unroll
+            for (int m = 0; m < R; ++m) c[m][i] = ok ? ((const CT*)a.src_crd[m])[start + off] : CT(0);
+            v[i] = ok ? ((const VT*)a.src_val)[start + off] : VT(0);
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            uint64_t key = 0;
+#pragma unroll
+            for (int m = 0; m < R; ++m)
+                if (a.key.mask[m]) key |= (((uint64_t)c[m][i] >> a.key.src_lo[m]) & a.key.mask[m]) << a.key.dst[m];
+            dg[i] = (uint32_t)(key >> a.lo) & dmask;
+        }
+
+        // ---- stable rank inside each wave: ballot-match the digit, count lanes below
+        for (int b = lane; b < kBins; b += 64) s_cnt[wave * kBins + b] = 0;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const bool ok = (wb + i * 64) < len;
+            const uint32_t d = dg[i];
+            uint64_t peers = ballot(ok);
+            for (int b = 0; b < a.bits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = ballot(bit);
+                peers &= bit ? bb : ~bb;
+            }
+            const uint32_t below = lanes_below(peers);
+            uint32_t old = 0;
+            if (ok) old = s_cnt[wave * kBins + d];
+            lp[i] = old + below;
+            if (ok && below == 0) s_cnt[wave * kBins + d] = old + (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+
+        // ---- per digit: wave prefixes, tile count, look-back for the global offset
+        {
+            const uint32_t b = tid;
+            uint32_t run = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t x = s_cnt[w * kBins + b];
+                s_cnt[w * kBins + b] = run;
+                run += x;
+            }
+            const uint32_t tcnt = run;
+            uint32_t* st = a.status + (size_t)t * kBins;
+            st_status(&st[b], (first ? kFlagP : kFlagA) | tcnt);
+            const uint32_t tstart = block_excl_scan(tcnt, s_tmp, nullptr);
+            const uint32_t hstart = block_excl_scan(hist[b], s_tmp + kWaves, nullptr);
+            uint32_t excl = 0;
+            if (!first) {
+                uint32_t j = t - 1, spins = 0;
+                for (;;) {
+                    const uint32_t w = ld_status(&a.status[(size_t)j * kBins + b]);
+                    const uint32_t f = w & ~kCntMask;
+                    if (f == 0) {
+                        if (++spins > kSpinLimit) {
+                            atomicOr(a.err, 1u);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    excl += w & kCntMask;
+                    if (f == kFlagP) break;
+                    --j;
+                }
+                st_status(&st[b], kFlagP | (excl + tcnt));
+            }
+            s_tstart[b] = tstart;
+            s_base[b] = seg_base + hstart + excl - tstart;
+            if (a.status_next) a.status_next[(size_t)t * kBins + b] = 0;
+        }
+        __syncthreads();
+
+        // ---- local slot of every record, then the digit of every local slot
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if ((wb + i * 64) < len) {
+                const uint32_t d = dg[i];
+                lp[i] += s_tstart[d] + s_cnt[wave * kBins + d];
+                s_dig[lp[i]] = (uint8_t)d;
+            }
+        }
+        __syncthreads();
+        uint32_t gp[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = i * kBlock + tid;
+            gp[i] = (j < len) ? s_base[s_dig[j]] + j : 0;
+        }
+
+        // ---- move every array through LDS: contiguous runs per digit on the way out
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            CT* sx = (CT*)s_x;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i)
+                if ((wb + i * 64) < len) sx[lp[i]] = c[m][i];
+            __syncthreads();
+            CT* dst = (CT*)a.dst_crd[m];
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t j = i * kBlock + tid;
+                if (j < len) dst[gp[i]] = sx[j];
+            }
+            __syncthreads();
+        }
+        {
+            VT* sx = (VT*)s_x;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i)
+                if ((wb + i * 64) < len) sx[lp[i]] = v[i];
+            __syncthreads();
+            VT* dst = (VT*)a.dst_val;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t j = i * kBlock + tid;
+                if (j < len) dst[gp[i]] = sx[j];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------ buckets
+
+// Segment starts: positions where the prefix (sigma_1..sigma_l) differs from the previous
+// record (Alg. 2's bucket discovery), compacted in order with a single-word look-back.
+template <typename CT>
+__global__ void __launch_bounds__(256) k_boundary(BoundArgs a) {
+    constexpr int ITEMS = kBoundTile / kBlock;
+    __shared__ uint32_t s_wsum[kWaves];
+    __shared__ uint32_t s_geo[2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) {
+        const uint32_t t = atomicAdd(a.tile_counter, 1u);
+        s_geo[0] = t;
+    }
+    __syncthreads();
+    const uint32_t t = s_geo[0];
+    const uint32_t start = t * kBoundTile;
+    if (start >= a.n) return;
+    const uint32_t len = min((uint32_t)kBoundTile, a.n - start);
+    const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
+    uint64_t flags[ITEMS];
+    uint32_t wcount = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t off = wb + i * 64;
+        const uint32_t e = start + off;
+        bool f = false;
+        if (off < len) {
+            f = (e == 0);
+            for (int j = 0; j < a.nprefix && !f; ++j) {
+                const CT* p = (const CT*)a.crd[a.prefix[j]];
+                f = p[e] != p[e - 1];
+            }
+        }
+        flags[i] = ballot(f);
+        wcount += (uint32_t)__popcll(flags[i]);
+    }
+    if (lane == 0) s_wsum[wave] = wcount;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += s_wsum[w];
+        uint32_t* st = a.status + t;
+        uint32_t excl = 0;
+        if (t == 0) {
+            st_status(st, kFlagP | tot);
+        } else {
+            st_status(st, kFlagA | tot);
+            uint32_t j = t - 1, spins = 0;
+            for (;;) {
+                const uint32_t w = ld_status(&a.status[j]);
+                const uint32_t f = w & ~kCntMask;
+                if (f == 0) {
+                    if (++spins > kSpinLimit) {
+                        atomicOr(a.err, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += w & kCntMask;
+                if (f == kFlagP) break;
+                --j;
+            }
+            st_status(st, kFlagP | (excl + tot));
+        }
+        s_geo[1] = excl;
+        if (start + len == a.n) {
+            *a.nb_out = excl + tot;
+            a.seg_start[excl + tot] = a.n;
+        }
+    }
+    __syncthreads();
+    uint32_t pos = s_geo[1];
+    for (int w = 0; w < wave; ++w) pos += s_wsum[w];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint64_t f = flags[i];
+        if ((f >> lane) & 1ull) a.seg_start[pos + lanes_below(f)] = start + wb + i * 64;
+        pos += (uint32_t)__popcll(f);
+    }
+}
+
+// Sort segments into three classes: tiny (left to the region pass), medium (one workgroup
+// each) and large (digit passes over tiles of the segment).
+__global__ void __launch_bounds__(256) k_classify(ClassArgs a) {
+    const uint32_t nb = *a.nb;
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nb; k += gridDim.x * kBlock) {
+        const uint32_t s = a.seg_start[k];
+        const uint32_t len = a.seg_start[k + 1] - s;
+        if (len <= (uint32_t)kTinyLen) continue;
+        if (len <= (uint32_t)kSmallCap) {
+            const uint32_t i = atomicAdd(a.nmed, 1u);
+            a.med[i] = make_uint2(s, len);
+        } else {
+            const uint32_t tiles = (len + a.tile - 1) / a.tile;
+            const unsigned long long old =
+                atomicAdd((unsigned long long*)a.large_ctl, (1ull << 32) | (unsigned long long)tiles);
+            const uint32_t idx = (uint32_t)(old >> 32);
+            SegRec rec;
+            rec.start = s;
+            rec.len = len;
+            rec.tile_base = (uint32_t)old;
+            rec.pad = 0;
+            a.large[idx] = rec;
+            uint32_t* h = a.seg_hist + (size_t)idx * a.hist_stride;
+            for (uint32_t i = 0; i < a.hist_stride; ++i) h[i] = 0;
+        }
+    }
+}
+
+// Stable sort of short runs of records entirely in LDS, by (segment number, group key).
+// Work items: the tiny segments starting in each region of kRegion records (their union
+// is one run of fewer than kSmallCap records), then every medium segment.
+template <typename CT, typename VT>
+__global__ void __launch_bounds__(256) k_small(SmallArgs a) {
+    constexpr int CAP = kSmallCap, ITEMS = CAP / kBlock;
+    __shared__ uint64_t s_key[CAP];   // keys, then staging of each array
+    __shared__ uint16_t s_ia[CAP], s_ib[CAP], s_seg[CAP];
+    __shared__ uint32_t s_cnt[kWaves * kBins];
+    __shared__ uint32_t s_bstart[kBins];
+    __shared__ uint32_t s_tmp[2 * kWaves];
+    __shared__ uint64_t s_red[2 * kWaves];
+    __shared__ uint32_t s_run[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t nb = *a.nb;
+
+    for (uint32_t item = blockIdx.x;; item += gridDim.x) {
+        const uint32_t nmed = *a.nmed;
+        if (item >= a.nregions + nmed) break;
+        if (tid == 0) {
+            uint32_t rs = 0, re = 0, sa = 0, se = 0;
+            if (item < a.nregions) {
+                const uint32_t lo = item * (uint32_t)kRegion, hi = min(a.n, lo + (uint32_t)kRegion);
+                // first segment starting at or after lo / hi (seg_start[nb] == n is a sentinel)
+                uint32_t l = 0, h = nb;
+                while (l < h) {
+                    const uint32_t m = (l + h) >> 1;
+                    if (a.seg_start[m] < lo) l = m + 1; else h = m;
+                }
+                sa = l;
+                h = nb;
+                while (l < h) {
+                    const uint32_t m = (l + h) >> 1;
+                    if (a.seg_start[m] < hi) l = m + 1; else h = m;
+                }
+                se = l;
+                // only the last segment starting here can be longer than the region
+                if (se > sa && a.seg_start[se] - a.seg_start[se - 1] > (uint32_t)kTinyLen) --se;
+                rs = a.seg_start[sa];
+                re = a.seg_start[se];
+            } else {
+                const uint2 md = a.med[item - a.nregions];
+                rs = md.x;
+                re = md.x + md.y;
+                sa = se = 0;
+            }
+            s_run[0] = rs;
+            s_run[1] = re;
+            s_run[2] = sa;
+            s_run[3] = se;
+        }
+        __syncthreads();
+        const uint32_t rs = s_run[0], L = s_run[1] - s_run[0];
+        const uint32_t sa = s_run[2], se = s_run[3];
+        if (L == 0) {
+            __syncthreads();
+            continue;
+        }
+        const bool region = item < a.nregions;
+        // ---- segment number of every record of the run
+        for (uint32_t j = tid; j < L; j += kBlock) s_seg[j] = 0;
+        __syncthreads();
+        if (region)
+            for (uint32_t s = sa + 1 + tid; s < se; s += kBlock) s_seg[a.seg_start[s] - rs] = 1;
+        __syncthreads();
+        {
+            // blocked inclusive scan: thread tid owns slots [tid*ITEMS, tid*ITEMS+ITEMS)
+            uint32_t loc[ITEMS], sum = 0;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t j = tid * ITEMS + i;
+                sum += (j < L) ? s_seg[j] : 0;
+                loc[i] = sum;
+            }
+            const uint32_t before = block_excl_scan(sum, s_tmp, nullptr);
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t j = tid * ITEMS + i;
+                if (j < L) s_seg[j] = (uint16_t)(before + loc[i]);
+            }
+        }
+        __syncthreads();
+        // ---- composite keys: (segment number << 52) | group key
+        uint64_t kor = 0, kand = ~0ull;
+        for (uint32_t j = tid; j < L; j += kBlock) {
+            CT c[8];
+            for (int m = 0; m < a.r; ++m) c[m] = a.key.mask[m] ? ((const CT*)a.src_crd[m])[rs + j] : CT(0);
+            const uint64_t key = compose_key<CT>(c, a.key, a.r) | ((uint64_t)s_seg[j] << 52);
+            s_key[j] = key;
+            s_ia[j] = (uint16_t)j;
+            kor |= key;
+            kand &= key;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            kor |= __shfl_xor(kor, o, 64);
+            kand &= __shfl_xor(kand, o, 64);
+        }
+        if (lane == 0) {
+            s_red[wave] = kor;
+            s_red[kWaves + wave] = kand;
+        }
+        __syncthreads();
+        kor = 0;
+        kand = ~0ull;
+        for (int w = 0; w < kWaves; ++w) {
+            kor |= s_red[w];
+            kand &= s_red[kWaves + w];
+        }
+        const uint64_t vary = kor ^ kand;
+        // ---- LSD passes over the bits that vary inside this run
+        uint16_t* cur = s_ia;
+        uint16_t* nxt = s_ib;
+        if (vary) {
+            const int lo = __builtin_ctzll(vary), hi = 63 - __builtin_clzll(vary);
+            for (int sh = lo; sh <= hi; sh += 8) {
+                const int nbits = min(8, hi - sh + 1);
+                const uint32_t dmask = (1u << nbits) - 1u;
+                for (int b = lane; b < kBins; b += 64) s_cnt[wave * kBins + b] = 0;
+                uint32_t dg[ITEMS], lp[ITEMS];
+                uint16_t sv[ITEMS];
+                const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t j = wb + i * 64;
+                    const bool ok = j < L;
+                    sv[i] = ok ? cur[j] : 0;
+                    dg[i] = ok ? (uint32_t)(s_key[sv[i]] >> sh) & dmask : 0;
+                }
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const bool ok = (wb + i * 64) < L;
+                    const uint32_t d = dg[i];
+                    uint64_t peers = ballot(ok);
+                    for (int b = 0; b < nbits; ++b) {
+                        const bool bit = (d >> b) & 1u;
+                        const uint64_t bb = ballot(bit);
+                        peers &= bit ? bb : ~bb;
+                    }
+                    const uint32_t below = lanes_below(peers);
+                    uint32_t old = 0;
+                    if (ok) old = s_cnt[wave * kBins + d];
+                    lp[i] = old + below;
+                    if (ok && below == 0) s_cnt[wave * kBins + d] = old + (uint32_t)__popcll(peers);
+                }
+                __syncthreads();
+                {
+                    const uint32_t b = tid;
+                    uint32_t run = 0;
+#pragma unroll
+                    for (int w = 0; w < kWaves; ++w) {
+                        const uint32_t x = s_cnt[w * kBins + b];
+                        s_cnt[w * kBins + b] = run;
+                        run += x;
+                    }
+                    s_bstart[b] = block_excl_scan(run, s_tmp, nullptr);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    if ((wb + i * 64) < L) {
+                        const uint32_t d = dg[i];
+                        nxt[lp[i] + s_bstart[d] + s_cnt[wave * kBins + d]] = sv[i];
+                    }
+                }
+                __syncthreads();
+                uint16_t* t = cur;
+                cur = nxt;
+                nxt = t;
+            }
+        }
+        // ---- move every array: stage the run in LDS, write it out in sorted order
+        for (int m = 0; m <= a.r; ++m) {
+            const bool isv = (m == a.r);
+            __syncthreads();
+            if ((isv ? sizeof(VT) : sizeof(CT)) == 8) {
+                const uint64_t* src = (const uint64_t*)(isv ? a.src_val : a.src_crd[m]) + rs;
+                uint64_t* dst = (uint64_t*)(isv ? a.dst_val : a.dst_crd[m]) + rs;
+                for (uint32_t j = tid; j < L; j += kBlock) s_key[j] = src[j];
+                __syncthreads();
+                for (uint32_t j = tid; j < L; j += kBlock) dst[j] = s_key[cur[j]];
+            } else {
+                const uint32_t* src = (const uint32_t*)(isv ? a.src_val : a.src_crd[m]) + rs;
+                uint32_t* dst = (uint32_t*)(isv ? a.dst_val : a.dst_crd[m]) + rs;
+                uint32_t* st = (uint32_t*)s_key;
+                for (uint32_t j = tid; j < L; j += kBlock) st[j] = src[j];
+                __syncthreads();
+                for (uint32_t j = tid; j < L; j += kBlock) dst[j] = st[cur[j]];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------ validation
+
+template <typename CT>
+__global__ void __launch_bounds__(256) k_validate(ValidateArgs a) {
+    uint32_t bad = 0;
+    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < a.n; e += gridDim.x * kBlock) {
+        for (int m = 0; m < a.r; ++m) {
+            const int64_t c = (int64_t)((const CT*)a.crd[m])[e];
+            if (c < 0 || c >= a.ext[m]) bad |= 1u;
+        }
+        if (e > 0) {
+            int cmp = 0;
+            for (int i = 0; i < a.r && cmp == 0; ++i) {
+                const CT* p = (const CT*)a.crd[a.in_order[i]];
+                const int64_t x = (int64_t)p[e - 1], y = (int64_t)p[e];
+                cmp = (x < y) ? -1 : (x > y ? 1 : 0);
+            }
+            if (cmp > 0) bad |= 2u;
+        }
+    }
+    if (bad) atomicOr(a.flags, bad);
+}
+
+// ------------------------------------------------------------------------------ CSF pack
+
+// Fiber boundaries of levels 1..r-1 (prefix sigma_1..sigma_d changes), numbered with an
+// (r-1)-word look-back; level r is the identity.  Writes crd_d and pos_d.
+template <typename CT, typename PT>
+__global__ void __launch_bounds__(256) k_csf(CsfArgs a) {
+    constexpr int ITEMS = 8, TILE = kBlock * ITEMS;
+    __shared__ uint32_t s_wsum[8][kWaves];
+    __shared__ uint32_t s_excl[8];
+    __shared__ uint32_t s_t;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int L = a.r - 1;  // counted levels
+    if (tid == 0) s_t = atomicAdd(a.tile_counter, 1u);
+    __syncthreads();
+    const uint32_t t = s_t;
+    const uint32_t start = t * TILE;
+    if (start >= a.n) return;
+    const uint32_t len = min((uint32_t)TILE, a.n - start);
+    const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
+    // level of the first differing mode: records j with first-difference level <= d start
+    // a level-d fiber.  lev = 0 for the first record (every level starts).
+    uint8_t lev[ITEMS];
+    uint32_t wcnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t off = wb + i * 64;
+        const uint32_t e = start + off;
+        int lv = a.r;  // no difference within levels 1..r-1
+        if (off < len) {
+            if (e == 0) {
+                lv = 0;
+            } else {
+                for (int d = 0; d < L; ++d) {
+                    const CT* p = (const CT*)a.crd[a.sigma[d]];
+                    if (p[e] != p[e - 1]) {
+                        lv = d;
+                        break;
+                    }
+                }
+            }
+        } else {
+            lv = 0xFF;
+        }
+        lev[i] = (uint8_t)lv;
+        for (int d = 0; d < L; ++d) wcnt[d] += (uint32_t)__popcll(ballot(off < len && lv <= d));
+    }
+    if (lane == 0)
+        for (int d = 0; d < L; ++d) s_wsum[d][wave] = wcnt[d];
+    __syncthreads();
+    if (tid < L) {
+        const int d = tid;
+        uint32_t tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += s_wsum[d][w];
+        uint32_t* st = a.status + (size_t)t * 8 + d;
+        uint32_t excl = 0;
+        if (t == 0) {
+            st_status(st, kFlagP | tot);
+        } else {
+            st_status(st, kFlagA | tot);
+            uint32_t j = t - 1, spins = 0;
+            for (;;) {
+                const uint32_t w = ld_status(&a.status[(size_t)j * 8 + d]);
+                const uint32_t f = w & ~kCntMask;
+                if (f == 0) {
+                    if (++spins > kSpinLimit) {
+                        atomicOr(a.err, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += w & kCntMask;
+                if (f == kFlagP) break;
+                --j;
+            }
+            st_status(st, kFlagP | (excl + tot));
+        }
+        s_excl[d] = excl;
+        if (start + len == a.n) a.fiber_counts[d + 1] = excl + tot;
+    }
+    if (tid == 0 && start + len == a.n) {
+        a.fiber_counts[0] = 1;
+        a.fiber_counts[a.r] = a.n;
+    }
+    __syncthreads();
+    // running fiber number per level for this thread's records
+    uint32_t base[8];
+    for (int d = 0; d < L; ++d) {
+        uint32_t b = s_excl[d];
+        for (int w = 0; w < wave; ++w) b += s_wsum[d][w];
+        base[d] = b;
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t off = wb + i * 64;
+        const uint32_t e = start + off;
+        const int lv = lev[i];
+        uint32_t fid[8];
+        for (int d = 0; d < L; ++d) {
+            const uint64_t m = ballot(off < len && lv <= d);
+            fid[d] = base[d] + lanes_below(m);  // fiber number if this record starts one
+            base[d] += (uint32_t)__popcll(m);
+        }
+        if (off < len) {
+            // level d (1-based) fiber starts here when lv <= d-1; leaves always start
+            for (int d = 1; d <= a.r; ++d) {
+                const bool starts = (d == a.r) || (lv <= d - 1);
+                if (!starts) continue;
+                const uint32_t f = (d == a.r) ? e : fid[d - 1];
+                ((CT*)a.out_crd[d - 1])[f] = ((const CT*)a.crd[a.sigma[d - 1]])[e];
+                // a new parent at level d-1 (or the root for d = 1) records its first child
+                if (d == 1) {
+                    if (e == 0) ((PT*)a.pos[0])[0] = 0;
+                } else if (lv <= d - 2) {
+                    ((PT*)a.pos[d - 1])[fid[d - 2]] = (PT)f;
+                }
+            }
+        }
+    }
+    if (tid == 0 && start + len == a.n) {
+        // closing offsets: pos_d[F_{d-1}] = F_d
+        ((PT*)a.pos[0])[1] = (PT)(L >= 1 ? (s_excl[0] + s_wsum[0][0] + s_wsum[0][1] + s_wsum[0][2] + s_wsum[0][3]) : a.n);
+        for (int d = 2; d <= a.r; ++d) {
+            const uint32_t fprev = s_excl[d - 2] + s_wsum[d - 2][0] + s_wsum[d - 2][1] + s_wsum[d - 2][2] + s_wsum[d - 2][3];
+            const uint32_t fcur = (d == a.r) ? a.n
+                : s_excl[d - 1] + s_wsum[d - 1][0] + s_wsum[d - 1][1] + s_wsum[d - 1][2] + s_wsum[d - 1][3];
+            ((PT*)a.pos[d - 1])[fprev] = (PT)fcur;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------ dispatch
+
+int g_cu = 0;
+
+template <typename K>
+int resident_blocks(K kernel) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess || per < 1) per = 1;
+    return per * device_cu_count();
+}
+
+template <int R, typename CT, typename VT, bool SEG>
+hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
+    constexpr int W = R * (int)(sizeof(CT) / 4) + (int)(sizeof(VT) / 4);
+    constexpr int ITEMS = W <= 6 ? 16 : 8;
+    auto kern = k_digit<R, CT, VT, ITEMS, SEG>;
+    static int resident = 0;
+    if (!resident) resident = resident_blocks(kern);
+    const uint32_t grid = (uint32_t)std::max(1, std::min<int>((int)a.ntiles, resident));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int R, typename CT, typename VT>
+hipError_t digit_r(const DigitArgs& a, hipStream_t s) {
+    return a.seg_mode ? digit_rs<R, CT, VT, true>(a, s) : digit_rs<R, CT, VT, false>(a, s);
+}
+
+template <typename CT, typename VT>
+hipError_t digit_cv(const DigitArgs& a, int r, hipStream_t s) {
+    switch (r) {
+        case 1: return digit_r<1, CT, VT>(a, s);
+        case 2: return digit_r<2, CT, VT>(a, s);
+        case 3: return digit_r<3, CT, VT>(a, s);
+        case 4: return digit_r<4, CT, VT>(a, s);
+        case 5: return digit_r<5, CT, VT>(a, s);
+        case 6: return digit_r<6, CT, VT>(a, s);
+        case 7: return digit_r<7, CT, VT>(a, s);
+        case 8: return digit_r<8, CT, VT>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename CT>
+hipError_t hist_c(const HistArgs& a, int r, int grid, hipStream_t s) {
+#define QSD_HIST_CASE(RR) \
+    case RR: hipLaunchKernelGGL((k_hist<RR, CT>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    switch (r) {
+        QSD_HIST_CASE(1) QSD_HIST_CASE(2) QSD_HIST_CASE(3) QSD_HIST_CASE(4)
+        QSD_HIST_CASE(5) QSD_HIST_CASE(6) QSD_HIST_CASE(7) QSD_HIST_CASE(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef QSD_HIST_CASE
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int device_cu_count() {
+    if (!g_cu) {
+        int dev = 0, cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+            g_cu = cu;
+        else
+            g_cu = 256;
+    }
+    return g_cu;
+}
+
+hipError_t launch_zero(const ZeroArgs& a, hipStream_t s) {
+    uint64_t mx = 0;
+    for (int i = 0; i < 4; ++i)
+        if (a.ptr[i]) mx = std::max(mx, a.words[i]);
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((mx + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_zero, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s) {
+    if (!bytes) return hipSuccess;
+    const bool aligned = (((uintptr_t)src | (uintptr_t)dst) & 15) == 0;
+    const uint64_t n16 = aligned ? bytes / 16 : 0;
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((bytes / 16 + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(kBlock), 0, s, (const uint4*)src, (uint4*)dst, n16,
+                       (const uint8_t*)src, (uint8_t*)dst, bytes);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist(const HistArgs& a, int r, int crd_bytes, int grid, hipStream_t s) {
+    return crd_bytes == 8 ? hist_c<uint64_t>(a, r, grid, s) : hist_c<uint32_t>(a, r, grid, s);
+}
+
+hipError_t launch_digit(const DigitArgs& a, int r, int crd_bytes, int val_bytes, hipStream_t s) {
+    if (crd_bytes == 8)
+        return val_bytes == 8 ? digit_cv<uint64_t, uint64_t>(a, r, s) : digit_cv<uint64_t, uint32_t>(a, r, s);
+    return val_bytes == 8 ? digit_cv<uint32_t, uint64_t>(a, r, s) : digit_cv<uint32_t, uint32_t>(a, r, s);
+}
+
+hipError_t launch_boundary(const BoundArgs& a, int crd_bytes, hipStream_t s) {
+    const uint32_t grid = (a.n + kBoundTile - 1) / kBoundTile;
+    if (!grid) return hipSuccess;
+    if (crd_bytes == 8)
+        hipLaunchKernelGGL(k_boundary<uint64_t>, dim3(grid), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_boundary<uint32_t>, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(const ClassArgs& a, uint32_t max_segments, hipStream_t s) {
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((max_segments + kBlock - 1) / kBlock, 4096));
+    hipLaunchKernelGGL(k_classify, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_small(const SmallArgs& a, int crd_bytes, int val_bytes, uint32_t max_items, hipStream_t s) {
+    if (!max_items) return hipSuccess;
+    const int cu = device_cu_count();
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(max_items, (uint32_t)cu * 8));
+    if (crd_bytes == 8) {
+        if (val_bytes == 8) hipLaunchKernelGGL((k_small<uint64_t, uint64_t>), dim3(grid), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_small<uint64_t, uint32_t>), dim3(grid), dim3(kBlock), 0, s, a);
+    } else {
+        if (val_bytes == 8) hipLaunchKernelGGL((k_small<uint32_t, uint64_t>), dim3(grid), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_small<uint32_t, uint32_t>), dim3(grid), dim3(kBlock), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const ValidateArgs& a, int crd_bytes, hipStream_t s) {
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((a.n + kBlock - 1) / kBlock, 4096));
+    if (crd_bytes == 8)
+        hipLaunchKernelGGL(k_validate<int64_t>, dim3(grid), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_validate<int32_t>, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_csf(const CsfArgs& a, int crd_bytes, hipStream_t s) {
+    const uint32_t grid = (a.n + kBlock * 8 - 1) / (kBlock * 8);
+    if (!grid) return hipSuccess;
+    if (crd_bytes == 8)
+        hipLaunchKernelGGL((k_csf<uint64_t, int64_t>), dim3(grid), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_csf<uint32_t, int32_t>), dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace qsd

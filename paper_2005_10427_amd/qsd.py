@@ -1,0 +1,240 @@
+"""ctypes binding of libqsd (include/qsd.h).  Argument marshalling only: every step of a
+transposition runs in the library's HIP kernels.  PyTorch supplies device memory and
+streams.  Loading fails loudly when the library has not been built.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqsd.so")
+
+QSD_OK = 0
+STATUS = {0: "ok", 1: "null", 2: "bad order", 3: "bad extent", 4: "too large", 5: "unsorted",
+          6: "coordinate range", 7: "workspace", 8: "unsupported", 9: "hip", 10: "device"}
+QSD_I32, QSD_I64 = 0, 1
+QSD_F32, QSD_F64 = 0, 1
+SCHED = {"auto": 0, "minimal": 1, "top2": 2, "lsd": 3}
+QSD_VALIDATE = 1
+MAX_ORDER = 8
+
+
+class QsdError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: qsd status {code} ({STATUS.get(code, '?')})")
+
+
+class qsd_desc(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("extents", ctypes.POINTER(ctypes.c_int64)), ("crd_type", ctypes.c_int),
+                ("val_type", ctypes.c_int), ("in_order", ctypes.POINTER(ctypes.c_int32)),
+                ("out_order", ctypes.POINTER(ctypes.c_int32)), ("flags", ctypes.c_uint32)]
+
+
+class qsd_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def load():
+    """Load libqsd.so (raises when it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.qsd_plan.argtypes = [ctypes.POINTER(qsd_desc), ctypes.c_int, ctypes.POINTER(_VP)]
+    lib.qsd_plan_destroy.argtypes = [_VP]
+    lib.qsd_plan_destroy.restype = None
+    lib.qsd_plan_workspace.argtypes = [_VP, ctypes.POINTER(ctypes.c_size_t)]
+    lib.qsd_plan_describe.argtypes = [_VP, ctypes.c_char_p, ctypes.c_size_t]
+    lib.qsd_transpose.argtypes = [_VP, ctypes.c_int64, ctypes.POINTER(_VP), _VP, ctypes.POINTER(_VP), _VP,
+                                  _VP, ctypes.c_size_t, _VP]
+    lib.qsd_csf_workspace.argtypes = [_VP, ctypes.POINTER(ctypes.c_size_t)]
+    lib.qsd_pack_csf.argtypes = [_VP, ctypes.c_int64, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                 ctypes.POINTER(_VP), _VP, _VP, ctypes.c_size_t, _VP]
+    lib.qsd_device_status.argtypes = [_VP, _VP, ctypes.POINTER(ctypes.c_uint32)]
+    lib.qsd_profile_start.argtypes = []
+    lib.qsd_profile_stop.argtypes = [ctypes.POINTER(qsd_kernel_stat), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32)]
+    lib.qsd_status_str.argtypes = [ctypes.c_int]
+    lib.qsd_status_str.restype = ctypes.c_char_p
+    for name in ("qsd_plan", "qsd_plan_workspace", "qsd_plan_describe", "qsd_transpose",
+                 "qsd_csf_workspace", "qsd_pack_csf", "qsd_device_status", "qsd_profile_start",
+                 "qsd_profile_stop"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code, where):
+    if code != QSD_OK:
+        raise QsdError(code, where)
+
+
+def _ptrs(seq):
+    arr = (_VP * MAX_ORDER)()
+    for i, p in enumerate(seq):
+        arr[i] = p
+    return arr
+
+
+# ---------------------------------------------------------------- raw C-ABI mirrors
+
+def qsd_plan(order, nnz, extents, crd_type, val_type, in_order, out_order, sched="minimal", flags=0):
+    """Returns an opaque plan handle (int)."""
+    lib = load()
+    r = int(order)
+    ext = (ctypes.c_int64 * max(r, 1))(*[int(x) for x in extents])
+    ino = (ctypes.c_int32 * max(r, 1))(*[int(x) for x in in_order])
+    outo = (ctypes.c_int32 * max(r, 1))(*[int(x) for x in out_order])
+    d = qsd_desc(r, int(nnz), ext, int(crd_type), int(val_type), ino, outo, int(flags))
+    h = _VP()
+    _check(lib.qsd_plan(ctypes.byref(d), SCHED[sched] if isinstance(sched, str) else int(sched),
+                        ctypes.byref(h)), "qsd_plan")
+    return h.value
+
+
+def qsd_plan_destroy(plan):
+    load().qsd_plan_destroy(plan)
+
+
+def qsd_plan_workspace(plan):
+    n = ctypes.c_size_t()
+    _check(load().qsd_plan_workspace(plan, ctypes.byref(n)), "qsd_plan_workspace")
+    return n.value
+
+
+def qsd_plan_describe(plan):
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(load().qsd_plan_describe(plan, buf, len(buf)), "qsd_plan_describe")
+    return buf.value.decode()
+
+
+def qsd_transpose(plan, nnz, in_crd, in_val, out_crd, out_val, ws, ws_bytes, stream):
+    """in_crd/out_crd: sequences of device pointers (ints); others device pointers/ints."""
+    _check(load().qsd_transpose(plan, int(nnz), _ptrs(in_crd), in_val, _ptrs(out_crd), out_val,
+                                ws, int(ws_bytes), stream), "qsd_transpose")
+
+
+def qsd_csf_workspace(plan):
+    n = ctypes.c_size_t()
+    _check(load().qsd_csf_workspace(plan, ctypes.byref(n)), "qsd_csf_workspace")
+    return n.value
+
+
+def qsd_pack_csf(plan, nnz, sorted_crd, pos, crd, fiber_counts, ws, ws_bytes, stream):
+    _check(load().qsd_pack_csf(plan, int(nnz), _ptrs(sorted_crd), _ptrs(pos), _ptrs(crd), fiber_counts,
+                               ws, int(ws_bytes), stream), "qsd_pack_csf")
+
+
+def qsd_device_status(ws, stream):
+    code = ctypes.c_uint32()
+    _check(load().qsd_device_status(ws, stream, ctypes.byref(code)), "qsd_device_status")
+    return code.value
+
+
+def qsd_profile_start():
+    _check(load().qsd_profile_start(), "qsd_profile_start")
+
+
+def qsd_profile_stop():
+    """{kind: (launches, total_ms, algorithmic_bytes)} of the launches since qsd_profile_start."""
+    out = (qsd_kernel_stat * 32)()
+    n = ctypes.c_int32()
+    _check(load().qsd_profile_stop(out, 32, ctypes.byref(n)), "qsd_profile_stop")
+    return {out[i].name.decode(): (out[i].launches, out[i].total_ms, out[i].bytes) for i in range(n.value)}
+
+
+def qsd_status_str(code):
+    return load().qsd_status_str(int(code)).decode()
+
+
+# ---------------------------------------------------------------- torch convenience layer
+
+class Plan:
+    """A plan plus the torch plumbing to call it on CUDA (HIP) tensors."""
+
+    def __init__(self, extents, in_order, out_order, nnz, crd_dtype="int32", val_dtype="float64",
+                 sched="minimal", flags=0):
+        import torch
+        self.torch = torch
+        self.r = len(extents)
+        self.extents = tuple(int(x) for x in extents)
+        self.in_order = tuple(int(x) for x in in_order)
+        self.out_order = tuple(int(x) for x in out_order)
+        self.nnz = int(nnz)
+        self.crd_dtype = getattr(torch, str(crd_dtype).replace("torch.", ""))
+        self.val_dtype = getattr(torch, str(val_dtype).replace("torch.", ""))
+        ct = QSD_I64 if self.crd_dtype == torch.int64 else QSD_I32
+        vt = QSD_F64 if self.val_dtype == torch.float64 else QSD_F32
+        self.handle = qsd_plan(self.r, self.nnz, self.extents, ct, vt, self.in_order, self.out_order,
+                               sched, flags)
+        self.ws_bytes = qsd_plan_workspace(self.handle)
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                qsd_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def describe(self):
+        return qsd_plan_describe(self.handle)
+
+    def workspace(self, device="cuda"):
+        if self._ws is None or self._ws.numel() < self.ws_bytes:
+            self._ws = self.torch.empty(max(self.ws_bytes, 1), dtype=self.torch.uint8, device=device)
+        return self._ws
+
+    def transpose(self, crd, val, out_crd=None, out_val=None, stream=None, nnz=None, ws=None):
+        """ws: optional uint8 device tensor of at least ws_bytes (shared between plans that
+        run one after the other on one stream)."""
+        torch = self.torch
+        n = int(val.shape[0]) if nnz is None else int(nnz)
+        dev = val.device
+        if out_crd is None:
+            out_crd = [torch.empty_like(c) for c in crd]
+        if out_val is None:
+            out_val = torch.empty_like(val)
+        if ws is None:
+            ws = self.workspace(dev)
+        elif ws.numel() < self.ws_bytes:
+            raise ValueError("workspace tensor smaller than the plan needs")
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        qsd_transpose(self.handle, n, [c.data_ptr() for c in crd], val.data_ptr(),
+                      [c.data_ptr() for c in out_crd], out_val.data_ptr(), ws.data_ptr(), self.ws_bytes,
+                      s.cuda_stream)
+        return out_crd, out_val
+
+    def device_status(self, stream=None):
+        s = stream if stream is not None else self.torch.cuda.current_stream()
+        return qsd_device_status(self.workspace().data_ptr(), s.cuda_stream)
+
+    def pack_csf(self, sorted_crd, nnz=None, stream=None):
+        """CSF of a tensor sorted under out_order: returns (pos list, crd list, fiber counts)."""
+        torch = self.torch
+        n = int(sorted_crd[0].shape[0]) if nnz is None else int(nnz)
+        dev = sorted_crd[0].device
+        pt = torch.int64 if self.crd_dtype == torch.int64 else torch.int32
+        pos = [torch.empty(2 if d == 0 else n + 1, dtype=pt, device=dev) for d in range(self.r)]
+        crd = [torch.empty(max(n, 1), dtype=self.crd_dtype, device=dev) for _ in range(self.r)]
+        fc = torch.empty(self.r + 1, dtype=torch.int64, device=dev)
+        wsb = qsd_csf_workspace(self.handle)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        qsd_pack_csf(self.handle, n, [c.data_ptr() for c in sorted_crd], [p.data_ptr() for p in pos],
+                     [c.data_ptr() for c in crd], fc.data_ptr(), ws.data_ptr(), wsb, s.cuda_stream)
+        s.synchronize()
+        counts = [int(x) for x in fc.cpu()]
+        pos = [pos[d][: counts[d] + 1] for d in range(self.r)]
+        crd = [crd[d][: counts[d + 1]] for d in range(self.r)]
+        return pos, crd, counts

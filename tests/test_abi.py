@@ -1,0 +1,144 @@
+"""Host-side checks of libqsd: it loads, exports every declared entry point, plans like the
+oracle planner, and rejects bad arguments before launching anything.  CPU only."""
+import itertools
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+from oracle import planner
+
+qsd = pytest.importorskip("paper_2005_10427_amd.qsd")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(qsd.LIB_PATH):
+        pytest.fail("libqsd.so is not built (run __graft_entry__.build())")
+    return qsd.load()
+
+
+def _declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            text = open(os.path.join(inc, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(qsd_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert "qsd_transpose" in names and "qsd_plan" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _parse(desc):
+    calls, groups, head = [], [], None
+    for line in desc.strip().splitlines():
+        kv = dict(tok.split("=", 1) for tok in line.split()[1:]) if " " in line else {}
+        if line.startswith("sched="):
+            head = dict(tok.split("=") for tok in line.split())
+        elif line.startswith("call "):
+            pre = tuple(int(x) for x in kv["prefix"].split(",") if x != "")
+            calls.append((pre, int(kv["mode"])))
+        elif line.startswith("group "):
+            groups.append(kv)
+    return head, calls, groups
+
+
+def _plan(r, tau, sigma, sched, extents=None, nnz=1000):
+    extents = extents or [7] * r
+    h = qsd.qsd_plan(r, nnz, extents, qsd.QSD_I32, qsd.QSD_F64, tau, sigma, sched)
+    try:
+        return _parse(qsd.qsd_plan_describe(h))
+    finally:
+        qsd.qsd_plan_destroy(h)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5])
+def test_minimal_plan_equals_oracle_alg3(lib, r):
+    for tau in itertools.permutations(range(r)):
+        for sigma in itertools.permutations(range(r)):
+            head, calls, groups = _plan(r, tau, sigma, "minimal")
+            assert head["sched"] == "MINIMAL"
+            want = planner.plan(tau, sigma)
+            assert calls == want, (tau, sigma)
+            # groups: maximal runs of calls sharing a prefix; keys most significant first
+            exp = []
+            for pre, m in want:
+                if exp and exp[-1][0] == pre:
+                    exp[-1][1].insert(0, m)
+                else:
+                    exp.append((pre, [m]))
+            got = [(tuple(int(x) for x in g["prefix"].split(",") if x), [int(x) for x in g["keys"].split(",")])
+                   for g in groups]
+            assert got == [(p, k) for p, k in exp]
+
+
+@pytest.mark.parametrize("r", [2, 3, 4, 5])
+def test_top2_and_lsd_plans(lib, r):
+    K = max(0, min(2, r - 2))
+    for tau in itertools.permutations(range(r)):
+        for sigma in itertools.permutations(range(r)):
+            head, calls, groups = _plan(r, tau, sigma, "top2")
+            assert int(head["K"]) == K
+            want, _ = planner.topk_plan(tau, sigma, K)
+            assert calls == want
+            head, calls, groups = _plan(r, tau, sigma, "lsd")
+            assert calls == planner.lsd_plan(sigma)
+            assert len(groups) == 1 and groups[0]["prefix"] == ""
+
+
+def test_digit_split_covers_key_bits(lib):
+    # 3-mode workload with 19/15/21-bit modes: (2,1,0) sorts modes 1 then 2 -> 36 key bits
+    head, calls, groups = _plan(3, (0, 1, 2), (2, 1, 0), "minimal", extents=[500000, 20000, 2000000])
+    assert calls == [((), 1), ((), 2)]
+    assert groups[0]["keys"] == "2,1" and int(groups[0]["bits"]) == 36 and int(groups[0]["passes"]) == 5
+    head, calls, groups = _plan(3, (0, 1, 2), (0, 2, 1), "minimal", extents=[500000, 20000, 2000000])
+    assert groups[0]["prefix"] == "0" and groups[0]["segmented"] == "1" and int(groups[0]["bits"]) == 21
+
+
+def test_extent_one_modes_need_no_pass(lib):
+    head, calls, groups = _plan(3, (0, 1, 2), (2, 1, 0), "minimal", extents=[5, 1, 1])
+    assert groups == []
+
+
+def test_bad_arguments_are_rejected_before_launch(lib):
+    with pytest.raises(qsd.QsdError) as e:
+        qsd.qsd_plan(3, 10, [4, 4, 4], qsd.QSD_I32, qsd.QSD_F64, (0, 1, 2), (0, 0, 1))
+    assert e.value.code == 2
+    with pytest.raises(qsd.QsdError) as e:
+        qsd.qsd_plan(3, 10, [4, 0, 4], qsd.QSD_I32, qsd.QSD_F64, (0, 1, 2), (0, 2, 1))
+    assert e.value.code == 3
+    with pytest.raises(qsd.QsdError) as e:
+        qsd.qsd_plan(3, 1 << 30, [4, 4, 4], qsd.QSD_I32, qsd.QSD_F64, (0, 1, 2), (0, 2, 1))
+    assert e.value.code == 4
+    with pytest.raises(qsd.QsdError) as e:
+        qsd.qsd_plan(9, 10, [4] * 9, qsd.QSD_I32, qsd.QSD_F64, tuple(range(9)), tuple(range(9)))
+    assert e.value.code == 2
+    with pytest.raises(qsd.QsdError) as e:
+        qsd.qsd_plan(2, 10, [1 << 32, 4], qsd.QSD_I32, qsd.QSD_F64, (0, 1), (1, 0))
+    assert e.value.code == 3
+    h = qsd.qsd_plan(3, 100, [4, 4, 4], qsd.QSD_I32, qsd.QSD_F64, (0, 1, 2), (2, 1, 0))
+    try:
+        ws = qsd.qsd_plan_workspace(h)
+        assert ws > 0
+        fake = [0x1000] * 3
+        with pytest.raises(qsd.QsdError) as e:  # workspace too small
+            qsd.qsd_transpose(h, 100, fake, 0x1000, fake, 0x1000, 0x1000, ws - 1, None)
+        assert e.value.code == 7
+        with pytest.raises(qsd.QsdError) as e:  # more nonzeros than planned
+            qsd.qsd_transpose(h, 101, fake, 0x1000, fake, 0x1000, 0x1000, ws, None)
+        assert e.value.code == 4
+        with pytest.raises(qsd.QsdError) as e:  # null coordinate pointer
+            qsd.qsd_transpose(h, 100, [0x1000, 0, 0x1000], 0x1000, fake, 0x1000, 0x1000, ws, None)
+        assert e.value.code == 1
+        qsd.qsd_transpose(h, 0, fake, 0x1000, fake, 0x1000, 0x1000, ws, None)  # nnz = 0: no-op
+    finally:
+        qsd.qsd_plan_destroy(h)
+    assert qsd.qsd_status_str(7).startswith("workspace")

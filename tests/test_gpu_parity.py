@@ -1,0 +1,207 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle: bit-exact outputs on the
+same seeded inputs, at sizes the oracle finishes in seconds, spanning many tiles and ragged
+tails, plus the edge cases (empty, single, duplicates, extent-1 modes, wide keys)."""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+from datagen import CONFIGS, config_tensor, make_tensor
+from oracle.transpose import transpose as oracle_transpose
+
+pytestmark = pytest.mark.gpu
+
+SCHEDS = ("minimal", "top2", "lsd")
+
+
+def note(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def dev(T):
+    import torch
+    crd = [torch.from_numpy(np.ascontiguousarray(c)).cuda() for c in T.crd]
+    val = torch.from_numpy(np.ascontiguousarray(T.val)).cuda()
+    return crd, val
+
+
+def gpu_transpose(qsd, T, sigma, sched="minimal", crd_val=None):
+    import torch
+    crd, val = crd_val if crd_val is not None else dev(T)
+    P = qsd.Plan(T.extents, T.in_order, sigma, max(T.nnz, 1), str(T.crd[0].dtype), str(T.val.dtype), sched)
+    out_crd, out_val = P.transpose(crd, val)
+    torch.cuda.synchronize()
+    assert P.device_status() == 0
+    return [c.cpu().numpy() for c in out_crd], out_val.cpu().numpy()
+
+
+def assert_bits_equal(got, want):
+    g_crd, g_val = got
+    w_crd, w_val = want
+    for m in range(len(w_crd)):
+        assert np.array_equal(g_crd[m], w_crd[m]), f"mode {m} differs"
+    u = np.uint64 if w_val.dtype.itemsize == 8 else np.uint32
+    assert np.array_equal(g_val.view(u), w_val.view(u)), "values differ"
+
+
+def check(qsd, T, sigma, sched="minimal", crd_val=None):
+    note(f"r={T.order} n={T.nnz} ext={T.extents} tau={T.in_order} sigma={sigma} sched={sched}")
+    got = gpu_transpose(qsd, T, sigma, sched, crd_val)
+    want = oracle_transpose(T.crd, T.val, sigma)
+    assert_bits_equal(got, want)
+
+
+def test_small_config_full_size(gpu_lib):
+    c = CONFIGS["small"]
+    T = config_tensor("small")
+    cv = dev(T)
+    for sigma in c["sigmas"]:
+        for sched in SCHEDS:
+            check(gpu_lib, T, sigma, sched, cv)
+
+
+def test_plain_config_shrunk_all_orders(gpu_lib):
+    T = config_tensor("plain", nnz=300_000)
+    cv = dev(T)
+    for sigma in CONFIGS["plain"]["sigmas"]:
+        for sched in SCHEDS:
+            check(gpu_lib, T, sigma, sched, cv)
+
+
+def test_wide_config_shrunk_all_orders(gpu_lib):
+    T = config_tensor("wide", nnz=400_000)
+    cv = dev(T)
+    for sigma in CONFIGS["wide"]["sigmas"]:
+        check(gpu_lib, T, sigma, "minimal", cv)
+    for sigma in CONFIGS["wide"]["sigmas"][::5]:
+        for sched in ("top2", "lsd"):
+            check(gpu_lib, T, sigma, sched, cv)
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 2047, 2048, 2049, 4095, 4096, 4097, 8193, 3 * 4096 - 1, 20000])
+def test_ragged_sizes_with_duplicates(gpu_lib, n):
+    rng = np.random.default_rng(n)
+    for trial in range(3):
+        r = int(rng.integers(2, 5))
+        ext = tuple(int(x) for x in rng.integers(1, 40, size=r))
+        tau = tuple(int(x) for x in rng.permutation(r))
+        T = make_tensor(ext, n, zipf=[float(rng.uniform(0, 1.5)) for _ in range(r)], in_order=tau,
+                        seed=int(rng.integers(1 << 30)), distinct=False)
+        for sigma in itertools.permutations(range(r)):
+            for sched in SCHEDS:
+                check(gpu_lib, T, sigma, sched)
+
+
+@pytest.mark.parametrize("crd,val", [("int32", "float32"), ("int64", "float64"), ("int64", "float32")])
+def test_types_and_orders_up_to_five(gpu_lib, crd, val):
+    rng = np.random.default_rng(hash((crd, val)) & 0xFFFF)
+    for r in (1, 2, 3, 4, 5):
+        ext = tuple(int(x) for x in rng.integers(2, 300, size=r))
+        tau = tuple(int(x) for x in rng.permutation(r))
+        T = make_tensor(ext, 30000, zipf=[1.2] * r, in_order=tau, crd_dtype=np.dtype(crd),
+                        val_dtype=np.dtype(val), seed=17 + r, distinct=False)
+        cv = dev(T)
+        sigmas = list(itertools.permutations(range(r)))
+        for sigma in (sigmas if r <= 3 else sigmas[::4]):
+            for sched in SCHEDS:
+                check(gpu_lib, T, sigma, sched, cv)
+
+
+def test_int64_wide_keys(gpu_lib):
+    """Extents beyond 2^32 (int64 coordinates): composite keys wider than 64 bits are cut
+    into sub-keys; bucketed groups with wide keys sort globally on (prefix, keys)."""
+    rng = np.random.default_rng(5)
+    ext = (3_000_000_000, 5_000_000_000, 70_000, 9)
+    n = 50_000
+    cols = [rng.integers(0, e, size=n, dtype=np.int64) for e in ext]
+    # a few heavy coordinates so that segments of every size class appear
+    cols[0][: n // 3] = 123_456_789
+    cols[1][: n // 5] = 42
+    tau = (0, 1, 2, 3)
+    p = np.lexsort([cols[m] for m in reversed(tau)])
+    from datagen import SynthTensor
+    T = SynthTensor(crd=[c[p] for c in cols], val=rng.standard_normal(n), extents=ext, in_order=tau)
+    cv = dev(T)
+    for sigma in itertools.permutations(range(4)):
+        for sched in SCHEDS:
+            check(gpu_lib, T, sigma, sched, cv)
+
+
+def test_extent_one_and_identity(gpu_lib):
+    T = make_tensor((1, 50, 1, 7), 3000, in_order=(0, 1, 2, 3), seed=3, distinct=False)
+    for sigma in [(0, 1, 2, 3), (2, 0, 3, 1), (3, 1, 0, 2), (1, 3, 2, 0)]:
+        for sched in SCHEDS:
+            check(gpu_lib, T, sigma, sched)
+
+
+def test_value_bits_survive(gpu_lib):
+    rng = np.random.default_rng(1)
+    T = make_tensor((30, 30), 5000, in_order=(0, 1), seed=4, distinct=False)
+    bits = T.val.view(np.uint64)
+    bits[::7] = 0x7FF8_0000_DEAD_BEEF  # NaN payloads
+    bits[3::11] = 0x8000_0000_0000_0000  # -0.0
+    check(gpu_lib, T, (1, 0))
+
+
+def test_empty(gpu_lib):
+    import torch
+    P = gpu_lib.Plan((5, 6), (0, 1), (1, 0), 10)
+    crd = [torch.zeros(1, dtype=torch.int32, device="cuda") for _ in range(2)]
+    val = torch.zeros(1, dtype=torch.float64, device="cuda")
+    P.transpose(crd, val, nnz=0)
+    torch.cuda.synchronize()
+
+
+def test_deterministic_repeats(gpu_lib):
+    import torch
+    T = config_tensor("plain", nnz=200_000, seed=99)
+    cv = dev(T)
+    P = gpu_lib.Plan(T.extents, T.in_order, (0, 2, 1), T.nnz)
+    ref = None
+    for rep in range(5):
+        oc, ov = P.transpose(*cv)
+        torch.cuda.synchronize()
+        h = [c.cpu().numpy().tobytes() for c in oc] + [ov.cpu().numpy().tobytes()]
+        if ref is None:
+            ref = h
+        assert h == ref
+
+
+def test_validation_errors(gpu_lib):
+    import torch
+    T = make_tensor((10, 10, 10), 500, in_order=(0, 1, 2), seed=8)
+    crd, val = dev(T)
+    P = gpu_lib.Plan(T.extents, (0, 1, 2), (2, 1, 0), T.nnz, flags=gpu_lib.QSD_VALIDATE)
+    P.transpose(crd, val)  # valid input passes
+    bad = [c.clone() for c in crd]
+    bad[1][7] = 10  # out of range
+    with pytest.raises(gpu_lib.QsdError) as e:
+        P.transpose(bad, val)
+    assert e.value.code == 6
+    uns = [c.flip(0).contiguous() for c in crd]
+    with pytest.raises(gpu_lib.QsdError) as e:
+        P.transpose(uns, val)
+    assert e.value.code == 5
+    torch.cuda.synchronize()
+
+
+def test_csf_pack_matches_oracle(gpu_lib):
+    import torch
+    from oracle import csf
+    rng = np.random.default_rng(12)
+    for trial in range(6):
+        r = int(rng.integers(1, 5))
+        ext = tuple(int(x) for x in rng.integers(1, 12, size=r))
+        sigma = tuple(int(x) for x in rng.permutation(r))
+        n = int(rng.integers(1, 20000))
+        T = make_tensor(ext, n, in_order=sigma, seed=trial, distinct=False)  # already sigma-sorted
+        note(f"csf r={r} n={n} ext={ext} sigma={sigma}")
+        P = gpu_lib.Plan(ext, sigma, sigma, n)
+        crd, _ = dev(T)
+        pos, lev, counts = P.pack_csf(crd)
+        want_pos, want_lev = csf.pack_csf([c.tolist() for c in T.crd], sigma)
+        assert counts[0] == 1 and counts[-1] == n
+        for d in range(r):
+            assert pos[d].cpu().tolist() == want_pos[d], f"pos level {d + 1}"
+            assert lev[d].cpu().tolist() == want_lev[d], f"crd level {d + 1}"
