@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -28,7 +29,8 @@ struct Layout {
     size_t hist_words = 0;
     size_t status[2] = {};
     size_t status_words = 0;  // per array
-    size_t seg_start = 0, bstatus = 0, bstatus_words = 0, med = 0, large = 0, seg_hist = 0;
+    size_t seg_start = 0, region_seg = 0, bstatus = 0, bstatus_words = 0, med = 0, large = 0, seg_hist = 0;
+    size_t tile_map = 0;
     uint32_t max_large = 0, max_med = 0, max_tiles_large = 0;
     size_t total = 0;
 };
@@ -43,6 +45,7 @@ struct qsd_plan_s {
     PlanData p;
     Layout L;
     int tile = 0;
+    int items = 16;
     std::vector<size_t> sub_hist_off;  // word offset of each global sub-key's histograms
     int nseg_groups = 0;
 };
@@ -53,7 +56,10 @@ void make_layout(qsd_plan_s* q) {
     const PlanData& p = q->p;
     Layout& L = q->L;
     const uint64_t N = (uint64_t)std::max<int64_t>(p.nnz, 1);
-    q->tile = digit_tile(p.r, p.crd_bytes, p.val_bytes);
+    int pref = 0;
+    if (const char* e = std::getenv("QSD_DIGIT_ITEMS")) pref = std::atoi(e);  // tuning override
+    q->items = digit_items(p.r, p.crd_bytes, p.val_bytes, pref);
+    q->tile = kBlock * q->items;
     const uint64_t T = (uint64_t)q->tile;
     size_t at = 0;
     L.ctl = at;
@@ -99,6 +105,10 @@ void make_layout(qsd_plan_s* q) {
     if (any_seg) {
         L.seg_start = at;
         at = up(at + (N + 2) * 4);
+        L.region_seg = at;
+        at = up(at + (cdiv(N, kRegion) + 2) * 4);
+        L.tile_map = at;
+        at = up(at + (size_t)L.max_tiles_large * 4);
         L.bstatus_words = cdiv(N, kBoundTile);
         L.bstatus = at;
         at = up(at + L.bstatus_words * 4 * q->nseg_groups);
@@ -242,7 +252,14 @@ qsd_status qsd_plan_workspace(qsd_plan_t plan, size_t* bytes) {
 
 qsd_status qsd_plan_describe(qsd_plan_t plan, char* buf, size_t len) {
     if (!plan || !buf) return QSD_ERR_NULL;
-    const std::string s = describe(plan->p);
+    std::string s = describe(plan->p);
+    const Layout& L = plan->L;
+    s += "layout tile=" + std::to_string(plan->tile) + " ctl=" + std::to_string(L.ctl) +
+         " status0=" + std::to_string(L.status[0]) + " status1=" + std::to_string(L.status[1]) +
+         " seg_start=" + std::to_string(L.seg_start) + " region_seg=" + std::to_string(L.region_seg) +
+         " tile_map=" + std::to_string(L.tile_map) + " med=" + std::to_string(L.med) +
+         " large=" + std::to_string(L.large) + " seg_hist=" + std::to_string(L.seg_hist) +
+         " total=" + std::to_string(L.total) + "\n";
     if (len == 0) return QSD_OK;
     const size_t n = std::min(len - 1, s.size());
     std::memcpy(buf, s.data(), n);
@@ -383,7 +400,7 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
                     da.tile_counter = ctl + kCtlPassCnt + q;
                     da.err = ctl + kCtlErr;
                     QSD_CK(timed(kDigit, 2.0 * n * (p.r * p.crd_bytes + p.val_bytes), stream,
-                                 [&] { return launch_digit(da, p.r, p.crd_bytes, p.val_bytes, stream); }));
+                                 [&] { return launch_digit(da, p.r, p.crd_bytes, p.val_bytes, plan->items, stream); }));
                     cur = dst;
                     ++h;
                     ++q;
@@ -396,6 +413,8 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
         const Bufs gsrc = cur;
         const Bufs gdst = hop_dst(h + np - 1);
         uint32_t* seg_start = (uint32_t*)(W + L.seg_start);
+        uint32_t* region_seg = (uint32_t*)(W + L.region_seg);
+        uint32_t* tile_map = (uint32_t*)(W + L.tile_map);
         uint32_t* bstatus = (uint32_t*)(W + L.bstatus) + (size_t)gseg * L.bstatus_words;
         uint2* med = (uint2*)(W + L.med);
         SegRec* large = (SegRec*)(W + L.large);
@@ -424,6 +443,7 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
         for (int i = 0; i < ba.nprefix; ++i) ba.prefix[i] = g.prefix[i];
         ba.n = n;
         ba.seg_start = seg_start;
+        ba.region_seg = region_seg;
         ba.status = bstatus;
         ba.tile_counter = ctl + kCtlBoundCnt;
         ba.nb_out = ctl + kCtlNb;
@@ -438,6 +458,7 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
         ca.med = med;
         ca.large_ctl = large_ctl;
         ca.large = large;
+        ca.tile_map = tile_map;
         ca.seg_hist = seg_hist;
         ca.hist_stride = (uint32_t)np * kBins;
         QSD_CK(timed(kClassify, 0, stream, [&] { return launch_classify(ca, n, stream); }));
@@ -455,7 +476,7 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
         sa.n = n;
         sa.nregions = (n + kRegion - 1) / kRegion;
         sa.seg_start = seg_start;
-        sa.nb = ctl + kCtlNb;
+        sa.region_seg = region_seg;
         sa.nmed = ctl + kCtlNMed;
         sa.med = med;
         const uint32_t small_items = sa.nregions + (uint32_t)std::min<uint64_t>(L.max_med, n / (kTinyLen + 1) + 1);
@@ -477,6 +498,7 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
         ha.status_zero = S[q % 2];
         ha.large_ctl = large_ctl;
         ha.large = large;
+        ha.tile_map = tile_map;
         QSD_CK(timed(kHistSeg, 0, stream, [&] { return launch_hist(ha, p.r, p.crd_bytes, device_cu_count() * 4, stream); }));
         const uint32_t max_tiles = (uint32_t)std::min<uint64_t>(L.max_tiles_large, (uint64_t)(n + T - 1) / T + n / (kSmallCap + 1) + 1);
         for (int i = 0; i < np; ++i) {
@@ -501,8 +523,9 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
             da.tile_counter = ctl + kCtlPassCnt + q;
             da.large_ctl = large_ctl;
             da.large = large;
+            da.tile_map = tile_map;
             da.err = ctl + kCtlErr;
-            QSD_CK(timed(kDigitSeg, 0, stream, [&] { return launch_digit(da, p.r, p.crd_bytes, p.val_bytes, stream); }));
+            QSD_CK(timed(kDigitSeg, 0, stream, [&] { return launch_digit(da, p.r, p.crd_bytes, p.val_bytes, plan->items, stream); }));
             cur = dst;
             ++h;
             ++q;

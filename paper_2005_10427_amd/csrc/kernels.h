@@ -36,14 +36,12 @@ struct SegRec {
     uint32_t start, len, tile_base, pad;
 };
 
-// Items per thread of the digit pass for a record of r coordinates: keeps the per-thread
-// record registers within budget.
-inline int digit_items(int r, int crd_bytes, int val_bytes) {
+// Items per thread of the digit pass (8 or 16): a whole record per item lives in registers,
+// so wide records take fewer items.  `pref` (0 = automatic) is a tuning override.
+inline int digit_items(int r, int crd_bytes, int val_bytes, int pref = 0) {
+    if (pref == 8 || pref == 16) return pref;
     const int words = r * (crd_bytes / 4) + val_bytes / 4;
     return words <= 6 ? 16 : 8;
-}
-inline int digit_tile(int r, int crd_bytes, int val_bytes) {
-    return kBlock * digit_items(r, crd_bytes, val_bytes);
 }
 
 struct DigitArgs {
@@ -63,6 +61,7 @@ struct DigitArgs {
     uint32_t* tile_counter;
     const uint64_t* large_ctl;  // segment mode
     const SegRec* large;        // segment mode
+    const uint32_t* tile_map;   // segment mode: large segment of every tile
     uint32_t* err;
 };
 
@@ -81,6 +80,7 @@ struct HistArgs {
     uint32_t status_words;      // global mode: words to zero
     const uint64_t* large_ctl;
     const SegRec* large;
+    const uint32_t* tile_map;
 };
 
 struct BoundArgs {
@@ -89,6 +89,7 @@ struct BoundArgs {
     int32_t prefix[8];
     uint32_t n;
     uint32_t* seg_start;        // nb + 1 entries written (seg_start[nb] = n)
+    uint32_t* region_seg;       // first segment starting in each kRegion-wide region (+ nb)
     uint32_t* status;           // one word per tile, zeroed beforehand
     uint32_t* tile_counter;
     uint32_t* nb_out;
@@ -103,6 +104,7 @@ struct ClassArgs {
     uint2* med;
     uint64_t* large_ctl;
     SegRec* large;
+    uint32_t* tile_map;
     uint32_t* seg_hist;         // zeroed per large segment
     uint32_t hist_stride;
 };
@@ -118,7 +120,7 @@ struct SmallArgs {
     uint32_t n;
     uint32_t nregions;
     const uint32_t* seg_start;
-    const uint32_t* nb;
+    const uint32_t* region_seg;
     const uint32_t* nmed;
     const uint2* med;
 };
@@ -153,7 +155,7 @@ struct CsfArgs {
 hipError_t launch_zero(const ZeroArgs& a, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_hist(const HistArgs& a, int r, int crd_bytes, int grid, hipStream_t s);
-hipError_t launch_digit(const DigitArgs& a, int r, int crd_bytes, int val_bytes, hipStream_t s);
+hipError_t launch_digit(const DigitArgs& a, int r, int crd_bytes, int val_bytes, int items, hipStream_t s);
 hipError_t launch_boundary(const BoundArgs& a, int crd_bytes, hipStream_t s);
 hipError_t launch_classify(const ClassArgs& a, uint32_t max_segments, hipStream_t s);
 hipError_t launch_small(const SmallArgs& a, int crd_bytes, int val_bytes, uint32_t max_items,

@@ -35,6 +35,14 @@ __device__ __forceinline__ void st_status(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+// Wait until this wave's LDS operations have completed (lgkmcnt(0); vmcnt and expcnt left at
+// their maximum).  The barrier of __syncthreads() does not wait for LDS atomics that return
+// nothing on this target, so a flush of LDS-atomic counters must wait explicitly first.
+__device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+__device__ __forceinline__ void sync_after_lds_atomics() {
+    lds_wait();
+    __syncthreads();
+}
 // number of set bits of m in lanes below this one
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
@@ -100,29 +108,54 @@ __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uin
 // segment.  Also clears the look-back words of the key's first digit pass.
 template <int R, typename CT>
 __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
+    constexpr int U = 8;  // records per thread per round (independent loads in flight)
     __shared__ uint32_t s_h[16 * kBins];
-    __shared__ uint32_t s_k;
+    __shared__ uint32_t s_pass[16];  // lo | bits << 8 of every pass
     const int tid = threadIdx.x;
     const int words = a.npass * kBins;
     for (int i = tid; i < words; i += kBlock) s_h[i] = 0;
-    const CT* src[8];
-#pragma unroll
-    for (int m = 0; m < R; ++m) src[m] = (const CT*)a.crd[m];
+    if (tid < a.npass) s_pass[tid] = (uint32_t)a.lo[tid] | ((uint32_t)a.bits[tid] << 8);
 
-    auto count = [&](uint32_t e) {
-        CT c[8];
+    // count the digits of records [lo, hi) with U loads per key mode in flight
+    auto count_range = [&](uint32_t lo, uint32_t hi) {
+        for (uint32_t base = lo; base < hi; base += kBlock * U) {
+            uint64_t key[U];
 #pragma unroll
-        for (int m = 0; m < R; ++m) c[m] = a.key.mask[m] ? src[m][e] : CT(0);
-        const uint64_t key = compose_key<CT>(c, a.key, R);
-        for (int p = 0; p < a.npass; ++p) {
-            const uint32_t d = (uint32_t)(key >> a.lo[p]) & ((1u << a.bits[p]) - 1u);
-            atomicAdd(&s_h[p * kBins + d], 1u);
+            for (int u = 0; u < U; ++u) key[u] = 0;
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                if (!a.key.mask[m]) continue;
+                const CT* src = (const CT*)a.crd[m];
+                CT c[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t e = base + u * kBlock + tid;
+                    c[u] = e < hi ? src[e] : CT(0);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    key[u] |= (((uint64_t)c[u] >> a.key.src_lo[m]) & a.key.mask[m]) << a.key.dst[m];
+            }
+            for (int p = 0; p < a.npass; ++p) {
+                const uint32_t pp = __builtin_amdgcn_readfirstlane(s_pass[p]);
+                const uint32_t lo = pp & 0xFF, mask = (1u << (pp >> 8)) - 1u;
+                uint32_t* h = s_h + p * kBins;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t e = base + u * kBlock + tid;
+                    if (e < hi) atomicAdd(&h[(uint32_t)(key[u] >> lo) & mask], 1u);
+                }
+            }
         }
     };
     __syncthreads();
     if (!a.seg_mode) {
-        for (uint32_t e = blockIdx.x * kBlock + tid; e < a.n; e += gridDim.x * kBlock) count(e);
-        __syncthreads();
+        const uint32_t chunk = kBlock * U;
+        const uint32_t nchunks = (a.n + chunk - 1) / chunk;
+        const uint32_t per = (nchunks + gridDim.x - 1) / gridDim.x;
+        const uint32_t c0 = blockIdx.x * per, c1 = min(nchunks, c0 + per);
+        if (c0 < c1) count_range(c0 * chunk, min(a.n, c1 * chunk));
+        sync_after_lds_atomics();
         for (int i = tid; i < words; i += kBlock) {
             const uint32_t c = s_h[i];
             if (c) atomicAdd(&a.hist[i], c);
@@ -131,25 +164,17 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
             a.status_zero[i] = 0;
         return;
     }
-    // segment mode: a static range of large-segment tiles per workgroup
-    const uint64_t lc = *a.large_ctl;
-    const uint32_t nL = (uint32_t)(lc >> 32), nT = (uint32_t)lc;
+    // segment mode: a static range of large-segment tiles per workgroup; histograms are
+    // flushed to the segment's block whenever the segment changes
+    const uint32_t nT = (uint32_t)*a.large_ctl;
     const uint32_t per = (nT + gridDim.x - 1) / gridDim.x;
     const uint32_t t0 = blockIdx.x * per, t1 = min(nT, t0 + per);
-    int cur = -1;
+    uint32_t cur = 0xFFFFFFFFu;
     for (uint32_t t = t0; t < t1; ++t) {
-        if (tid == 0) {
-            uint32_t lo = 0, hi = nL;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (a.large[mid].tile_base <= t) lo = mid; else hi = mid;
-            }
-            s_k = lo;
-        }
-        __syncthreads();
-        const int k = (int)s_k;
+        const uint32_t k = a.tile_map[t];
         if (k != cur) {
-            if (cur >= 0) {
+            sync_after_lds_atomics();
+            if (cur != 0xFFFFFFFFu) {
                 for (int i = tid; i < words; i += kBlock) {
                     const uint32_t c = s_h[i];
                     if (c) atomicAdd(&a.hist[(size_t)cur * a.hist_stride + i], c);
@@ -157,16 +182,16 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
                 }
             }
             cur = k;
+            __syncthreads();
         }
-        __syncthreads();
         const SegRec s = a.large[k];
         const uint32_t start = s.start + (t - s.tile_base) * a.tile;
         const uint32_t end = min(s.start + s.len, start + a.tile);
-        for (uint32_t e = start + tid; e < end; e += kBlock) count(e);
+        count_range(start, end);
         a.status_zero[(size_t)t * kBins + tid] = 0;
-        __syncthreads();
     }
-    if (cur >= 0) {
+    sync_after_lds_atomics();
+    if (cur != 0xFFFFFFFFu) {
         for (int i = tid; i < words; i += kBlock) {
             const uint32_t c = s_h[i];
             if (c) atomicAdd(&a.hist[(size_t)cur * a.hist_stride + i], c);
@@ -175,6 +200,88 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
 }
 
 // ------------------------------------------------------------------------------ digit pass
+
+constexpr int kLookWin = 8;
+
+// Decoupled look-back for one digit: sum the counts of the predecessors of tile t back to
+// the nearest one that has published an inclusive prefix.  kLookWin status words are read
+// per round trip; `lowest` (the first tile of the segment) always publishes a prefix.
+__device__ __forceinline__ uint32_t look_back(const uint32_t* status, uint32_t t, uint32_t lowest,
+                                              uint32_t b, uint32_t* err) {
+    uint32_t excl = 0, spins = 0;
+    uint32_t j = t - 1;  // next predecessor to read
+    {
+        // usually the immediate predecessor has already published its prefix
+        const uint32_t w = ld_status(&status[(size_t)j * kBins + b]);
+        const uint32_t f = w & ~kCntMask;
+        if (f == kFlagP) return w & kCntMask;
+        if (f == kFlagA) {
+            excl = w & kCntMask;
+            --j;
+        }
+    }
+    for (;;) {
+        const uint32_t avail = j - lowest + 1;
+        uint32_t w[kLookWin];
+#pragma unroll
+        for (int i = 0; i < kLookWin; ++i)
+            w[i] = ((uint32_t)i < avail) ? ld_status(&status[(size_t)(j - i) * kBins + b]) : 0u;
+        uint32_t used = 0;
+        bool done = false, stalled = false;
+#pragma unroll
+        for (int i = 0; i < kLookWin; ++i) {
+            if (done || stalled || (uint32_t)i >= avail) continue;
+            const uint32_t f = w[i] & ~kCntMask;
+            if (f == 0) {
+                stalled = true;
+                continue;
+            }
+            excl += w[i] & kCntMask;
+            ++used;
+            if (f == kFlagP) done = true;
+        }
+        if (done) return excl;
+        j -= used;
+        if (stalled) {
+            if (++spins > kSpinLimit) {
+                atomicOr(err, 1u);
+                return excl;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+}
+
+// Move one array of the tile: registers -> LDS (local slot lp) -> global (slot gp), with
+// the next array's loads issued before the barrier.
+template <typename T, int ITEMS>
+__device__ __forceinline__ void load_items(const T* __restrict__ src, uint32_t start, uint32_t len,
+                                           uint32_t wb, T (&x)[ITEMS]) {
+    const T* tile = src + start;  // uniform base; per-item offsets stay small
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t off = wb + i * 64;
+        x[i] = off < len ? tile[off] : T(0);
+    }
+}
+
+template <typename T, int ITEMS>
+__device__ __forceinline__ void stage_items(T* sx, uint32_t len, uint32_t wb, const T (&x)[ITEMS],
+                                            const uint32_t (&lp)[ITEMS]) {
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        if (wb + i * 64 < len) sx[lp[i]] = x[i];
+}
+
+template <typename T, int ITEMS>
+__device__ __forceinline__ void drain_items(const T* sx, T* __restrict__ dst, uint32_t len,
+                                            const uint32_t (&gp)[ITEMS]) {
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = i * kBlock + threadIdx.x;
+        if (j < len) dst[gp[i]] = sx[j];
+    }
+}
 
 template <int R, typename CT, typename VT, int ITEMS, bool SEG>
 __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
@@ -185,7 +292,7 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
     __shared__ uint32_t s_base[kBins];           // global slot of local slot 0 of each digit
     __shared__ uint8_t s_dig[TILE];
     __shared__ uint32_t s_tmp[2 * kWaves];
-    __shared__ uint32_t s_geo[5];                // tile id, start, len, segment base, k
+    __shared__ uint32_t s_geo[6];                // tile, start, len, segment base, k, first tile
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t dmask = (1u << a.bits) - 1u;
@@ -193,19 +300,14 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
     for (;;) {
         if (tid == 0) {
             const uint32_t t = atomicAdd(a.tile_counter, 1u);
-            uint32_t ntiles = a.ntiles, start = 0, len = 0, base = 0, k = 0;
+            uint32_t ntiles = a.ntiles, start = 0, len = 0, base = 0, k = 0, lowest = 0;
             if (SEG) {
-                const uint64_t lc = *a.large_ctl;
-                ntiles = (uint32_t)lc;
+                ntiles = (uint32_t)*a.large_ctl;
                 if (t < ntiles) {
-                    uint32_t lo = 0, hi = (uint32_t)(lc >> 32);
-                    while (hi - lo > 1) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (a.large[mid].tile_base <= t) lo = mid; else hi = mid;
-                    }
-                    const SegRec s = a.large[lo];
-                    k = lo;
+                    k = a.tile_map[t];
+                    const SegRec s = a.large[k];
                     base = s.start;
+                    lowest = s.tile_base;
                     start = s.start + (t - s.tile_base) * TILE;
                     len = min((uint32_t)TILE, s.start + s.len - start);
                 }
@@ -218,27 +320,28 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
             s_geo[2] = len;
             s_geo[3] = base;
             s_geo[4] = k;
+            s_geo[5] = lowest;
         }
         __syncthreads();
-        const uint32_t t = s_geo[0];
+        // tile geometry is uniform: keep it in scalar registers
+        const uint32_t t = __builtin_amdgcn_readfirstlane(s_geo[0]);
         if (t == 0xFFFFFFFFu) break;
-        const uint32_t start = s_geo[1], len = s_geo[2], seg_base = s_geo[3], k = s_geo[4];
-        const bool first = SEG ? (start == seg_base) : (t == 0);
+        const uint32_t start = __builtin_amdgcn_readfirstlane(s_geo[1]);
+        const uint32_t len = __builtin_amdgcn_readfirstlane(s_geo[2]);
+        const uint32_t seg_base = __builtin_amdgcn_readfirstlane(s_geo[3]);
+        const uint32_t k = __builtin_amdgcn_readfirstlane(s_geo[4]);
+        const uint32_t lowest = __builtin_amdgcn_readfirstlane(s_geo[5]);
+        const bool first = (t == lowest);
         const uint32_t* hist = a.hist + (size_t)k * a.hist_stride;
+        const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;  // wave w owns a contiguous slice
 
-        // ---- load whole records (wave w owns the contiguous slice [w*64*ITEMS, (w+1)*64*ITEMS))
+        // ---- whole records into registers (all loads in flight at once), then the digit
         CT c[R][ITEMS];
         VT v[ITEMS];
         uint32_t dg[ITEMS], lp[ITEMS];
-        const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t off = wb + i * 64;
-            const bool ok = off < len;
-#pragma unroll
-            for (int m = 0; m < R; ++m) c[m][i] = ok ? ((const CT*)a.src_crd[m])[start + off] : CT(0);
-            v[i] = ok ? ((const VT*)a.src_val)[start + off] : VT(0);
-        }
+        for (int m = 0; m < R; ++m) load_items<CT, ITEMS>((const CT*)a.src_crd[m], start, len, wb, c[m]);
+        load_items<VT, ITEMS>((const VT*)a.src_val, start, len, wb, v);
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             uint64_t key = 0;
@@ -285,22 +388,7 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
             const uint32_t hstart = block_excl_scan(hist[b], s_tmp + kWaves, nullptr);
             uint32_t excl = 0;
             if (!first) {
-                uint32_t j = t - 1, spins = 0;
-                for (;;) {
-                    const uint32_t w = ld_status(&a.status[(size_t)j * kBins + b]);
-                    const uint32_t f = w & ~kCntMask;
-                    if (f == 0) {
-                        if (++spins > kSpinLimit) {
-                            atomicOr(a.err, 1u);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
-                    }
-                    excl += w & kCntMask;
-                    if (f == kFlagP) break;
-                    --j;
-                }
+                excl = look_back(a.status, t, lowest, b, a.err);
                 st_status(&st[b], kFlagP | (excl + tcnt));
             }
             s_tstart[b] = tstart;
@@ -329,33 +417,15 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
         // ---- move every array through LDS: contiguous runs per digit on the way out
 #pragma unroll
         for (int m = 0; m < R; ++m) {
-            CT* sx = (CT*)s_x;
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i)
-                if ((wb + i * 64) < len) sx[lp[i]] = c[m][i];
+            stage_items<CT, ITEMS>((CT*)s_x, len, wb, c[m], lp);
             __syncthreads();
-            CT* dst = (CT*)a.dst_crd[m];
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const uint32_t j = i * kBlock + tid;
-                if (j < len) dst[gp[i]] = sx[j];
-            }
+            drain_items<CT, ITEMS>((const CT*)s_x, (CT*)a.dst_crd[m], len, gp);
             __syncthreads();
         }
-        {
-            VT* sx = (VT*)s_x;
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i)
-                if ((wb + i * 64) < len) sx[lp[i]] = v[i];
-            __syncthreads();
-            VT* dst = (VT*)a.dst_val;
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const uint32_t j = i * kBlock + tid;
-                if (j < len) dst[gp[i]] = sx[j];
-            }
-            __syncthreads();
-        }
+        stage_items<VT, ITEMS>((VT*)s_x, len, wb, v, lp);
+        __syncthreads();
+        drain_items<VT, ITEMS>((const VT*)s_x, (VT*)a.dst_val, len, gp);
+        __syncthreads();
     }
 }
 
@@ -429,6 +499,7 @@ __global__ void __launch_bounds__(256) k_boundary(BoundArgs a) {
         if (start + len == a.n) {
             *a.nb_out = excl + tot;
             a.seg_start[excl + tot] = a.n;
+            a.region_seg[(a.n + kRegion - 1) / kRegion] = excl + tot;
         }
     }
     __syncthreads();
@@ -437,7 +508,10 @@ __global__ void __launch_bounds__(256) k_boundary(BoundArgs a) {
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint64_t f = flags[i];
-        if ((f >> lane) & 1ull) a.seg_start[pos + lanes_below(f)] = start + wb + i * 64;
+        const uint32_t e = start + wb + i * 64;
+        const uint32_t before = pos + lanes_below(f);  // segments starting before e
+        if ((f >> lane) & 1ull) a.seg_start[before] = e;
+        if (wb + i * 64 < len && e % (uint32_t)kRegion == 0) a.region_seg[e / kRegion] = before;
         pos += (uint32_t)__popcll(f);
     }
 }
@@ -464,6 +538,7 @@ __global__ void __launch_bounds__(256) k_classify(ClassArgs a) {
             rec.tile_base = (uint32_t)old;
             rec.pad = 0;
             a.large[idx] = rec;
+            for (uint32_t i = 0; i < tiles; ++i) a.tile_map[rec.tile_base + i] = idx;
             uint32_t* h = a.seg_hist + (size_t)idx * a.hist_stride;
             for (uint32_t i = 0; i < a.hist_stride; ++i) h[i] = 0;
         }
@@ -484,7 +559,6 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
     __shared__ uint64_t s_red[2 * kWaves];
     __shared__ uint32_t s_run[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t nb = *a.nb;
 
     for (uint32_t item = blockIdx.x;; item += gridDim.x) {
         const uint32_t nmed = *a.nmed;
@@ -492,20 +566,9 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
         if (tid == 0) {
             uint32_t rs = 0, re = 0, sa = 0, se = 0;
             if (item < a.nregions) {
-                const uint32_t lo = item * (uint32_t)kRegion, hi = min(a.n, lo + (uint32_t)kRegion);
-                // first segment starting at or after lo / hi (seg_start[nb] == n is a sentinel)
-                uint32_t l = 0, h = nb;
-                while (l < h) {
-                    const uint32_t m = (l + h) >> 1;
-                    if (a.seg_start[m] < lo) l = m + 1; else h = m;
-                }
-                sa = l;
-                h = nb;
-                while (l < h) {
-                    const uint32_t m = (l + h) >> 1;
-                    if (a.seg_start[m] < hi) l = m + 1; else h = m;
-                }
-                se = l;
+                // segments starting in [item*kRegion, (item+1)*kRegion): sa .. se-1
+                sa = a.region_seg[item];
+                se = a.region_seg[item + 1];
                 // only the last segment starting here can be longer than the region
                 if (se > sa && a.seg_start[se] - a.seg_start[se - 1] > (uint32_t)kTinyLen) --se;
                 rs = a.seg_start[sa];
@@ -828,10 +891,8 @@ int resident_blocks(K kernel) {
     return per * device_cu_count();
 }
 
-template <int R, typename CT, typename VT, bool SEG>
+template <int R, typename CT, typename VT, int ITEMS, bool SEG>
 hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
-    constexpr int W = R * (int)(sizeof(CT) / 4) + (int)(sizeof(VT) / 4);
-    constexpr int ITEMS = W <= 6 ? 16 : 8;
     auto kern = k_digit<R, CT, VT, ITEMS, SEG>;
     static int resident = 0;
     if (!resident) resident = resident_blocks(kern);
@@ -841,21 +902,23 @@ hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
 }
 
 template <int R, typename CT, typename VT>
-hipError_t digit_r(const DigitArgs& a, hipStream_t s) {
-    return a.seg_mode ? digit_rs<R, CT, VT, true>(a, s) : digit_rs<R, CT, VT, false>(a, s);
+hipError_t digit_r(const DigitArgs& a, int items, hipStream_t s) {
+    if (items == 16)
+        return a.seg_mode ? digit_rs<R, CT, VT, 16, true>(a, s) : digit_rs<R, CT, VT, 16, false>(a, s);
+    return a.seg_mode ? digit_rs<R, CT, VT, 8, true>(a, s) : digit_rs<R, CT, VT, 8, false>(a, s);
 }
 
 template <typename CT, typename VT>
-hipError_t digit_cv(const DigitArgs& a, int r, hipStream_t s) {
+hipError_t digit_cv(const DigitArgs& a, int r, int items, hipStream_t s) {
     switch (r) {
-        case 1: return digit_r<1, CT, VT>(a, s);
-        case 2: return digit_r<2, CT, VT>(a, s);
-        case 3: return digit_r<3, CT, VT>(a, s);
-        case 4: return digit_r<4, CT, VT>(a, s);
-        case 5: return digit_r<5, CT, VT>(a, s);
-        case 6: return digit_r<6, CT, VT>(a, s);
-        case 7: return digit_r<7, CT, VT>(a, s);
-        case 8: return digit_r<8, CT, VT>(a, s);
+        case 1: return digit_r<1, CT, VT>(a, items, s);
+        case 2: return digit_r<2, CT, VT>(a, items, s);
+        case 3: return digit_r<3, CT, VT>(a, items, s);
+        case 4: return digit_r<4, CT, VT>(a, items, s);
+        case 5: return digit_r<5, CT, VT>(a, items, s);
+        case 6: return digit_r<6, CT, VT>(a, items, s);
+        case 7: return digit_r<7, CT, VT>(a, items, s);
+        case 8: return digit_r<8, CT, VT>(a, items, s);
     }
     return hipErrorInvalidValue;
 }
@@ -910,10 +973,10 @@ hipError_t launch_hist(const HistArgs& a, int r, int crd_bytes, int grid, hipStr
     return crd_bytes == 8 ? hist_c<uint64_t>(a, r, grid, s) : hist_c<uint32_t>(a, r, grid, s);
 }
 
-hipError_t launch_digit(const DigitArgs& a, int r, int crd_bytes, int val_bytes, hipStream_t s) {
+hipError_t launch_digit(const DigitArgs& a, int r, int crd_bytes, int val_bytes, int items, hipStream_t s) {
     if (crd_bytes == 8)
-        return val_bytes == 8 ? digit_cv<uint64_t, uint64_t>(a, r, s) : digit_cv<uint64_t, uint32_t>(a, r, s);
-    return val_bytes == 8 ? digit_cv<uint32_t, uint64_t>(a, r, s) : digit_cv<uint32_t, uint32_t>(a, r, s);
+        return val_bytes == 8 ? digit_cv<uint64_t, uint64_t>(a, r, items, s) : digit_cv<uint64_t, uint32_t>(a, r, items, s);
+    return val_bytes == 8 ? digit_cv<uint32_t, uint64_t>(a, r, items, s) : digit_cv<uint32_t, uint32_t>(a, r, items, s);
 }
 
 hipError_t launch_boundary(const BoundArgs& a, int crd_bytes, hipStream_t s) {
