@@ -109,12 +109,20 @@ __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uin
 template <int R, typename CT>
 __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
     constexpr int U = 8;  // records per thread per round (independent loads in flight)
-    __shared__ uint32_t s_h[16 * kBins];
-    __shared__ uint32_t s_pass[16];  // lo | bits << 8 of every pass
-    const int tid = threadIdx.x;
-    const int words = a.npass * kBins;
+    constexpr int MAXP = 16;
+    __shared__ uint32_t s_h[MAXP * kBins + kBins];  // + one spare block for out-of-range items
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int npass = a.npass;
+    const int words = npass * kBins;
     for (int i = tid; i < words; i += kBlock) s_h[i] = 0;
-    if (tid < a.npass) s_pass[tid] = (uint32_t)a.lo[tid] | ((uint32_t)a.bits[tid] << 8);
+    // per-pass shift and mask, uniform: kept in scalar registers for the whole kernel
+    uint32_t plo[MAXP], pmask[MAXP];
+#pragma unroll
+    for (int p = 0; p < MAXP; ++p) {
+        plo[p] = p < npass ? (uint32_t)a.lo[p] : 0u;
+        pmask[p] = p < npass ? (1u << a.bits[p]) - 1u : 0u;
+    }
+    const uint32_t spare = MAXP * kBins;  // items past the end count into the spare block
 
     // count the digits of records [lo, hi) with U loads per key mode in flight
     auto count_range = [&](uint32_t lo, uint32_t hi) {
@@ -136,14 +144,23 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
                 for (int u = 0; u < U; ++u)
                     key[u] |= (((uint64_t)c[u] >> a.key.src_lo[m]) & a.key.mask[m]) << a.key.dst[m];
             }
-            for (int p = 0; p < a.npass; ++p) {
-                const uint32_t pp = __builtin_amdgcn_readfirstlane(s_pass[p]);
-                const uint32_t lo = pp & 0xFF, mask = (1u << (pp >> 8)) - 1u;
-                uint32_t* h = s_h + p * kBins;
+#pragma unroll
+            for (int p = 0; p < MAXP; ++p) {
+                if (p >= npass) break;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const uint32_t e = base + u * kBlock + tid;
-                    if (e < hi) atomicAdd(&h[(uint32_t)(key[u] >> lo) & mask], 1u);
+                    const uint32_t slot = e < hi ? p * kBins + ((uint32_t)(key[u] >> plo[p]) & pmask[p]) : spare;
+                    // sorted inputs put long runs of one digit in consecutive lanes: add each
+                    // run once, from its first lane, instead of one conflicting atomic per lane
+                    const uint32_t prev = __shfl_up(slot, 1, 64);
+                    const bool head = (lane == 0) || (prev != slot);
+                    const uint64_t heads = ballot(head);
+                    if (head) {
+                        const uint64_t after = (lane == 63) ? 0ull : (heads >> (lane + 1));
+                        const uint32_t run = after ? (uint32_t)__builtin_ctzll(after) + 1u : 64u - lane;
+                        atomicAdd(&s_h[slot], run);
+                    }
                 }
             }
         }
@@ -202,6 +219,42 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
 // ------------------------------------------------------------------------------ digit pass
 
 constexpr int kLookWin = 8;
+
+// Decoupled look-back done by one whole wave for one counter: lane l reads the status of
+// tile j - l, so 64 predecessors are inspected per round trip.  Statuses are at
+// status[tile * stride + slot]; `lowest` is the first tile (it always publishes a prefix).
+// Every lane returns the same exclusive prefix.
+__device__ __forceinline__ uint32_t wave_look_back(const uint32_t* status, uint32_t t, uint32_t stride,
+                                                   uint32_t slot, uint32_t lowest, uint32_t* err) {
+    const int lane = threadIdx.x & 63;
+    uint32_t excl = 0, spins = 0;
+    uint32_t j = t - 1;  // most recent predecessor not yet accounted for
+    for (;;) {
+        const uint32_t avail = j - lowest + 1;
+        const uint32_t w = (uint32_t)lane < avail ? ld_status(&status[(size_t)(j - lane) * stride + slot]) : 0u;
+        const uint32_t f = w & ~kCntMask;
+        const uint64_t notready = ballot((uint32_t)lane < avail && f == 0);
+        const uint64_t prefix = ballot(f == kFlagP);
+        const uint32_t stop_nr = notready ? (uint32_t)__builtin_ctzll(notready) : 64u;
+        const uint32_t stop_p = prefix ? (uint32_t)__builtin_ctzll(prefix) : 64u;
+        // lanes before the first not-ready one are usable; include the first prefix if it
+        // comes before that
+        const uint32_t use = stop_p < stop_nr ? stop_p + 1 : min(stop_nr, min(avail, 64u));
+        uint32_t part = (uint32_t)lane < use ? (w & kCntMask) : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        excl += part;
+        if (stop_p < stop_nr) return excl;
+        j -= use;
+        if (stop_nr < 64 && stop_nr < avail) {
+            if (++spins > kSpinLimit) {
+                if (lane == 0) atomicOr(err, 1u);
+                return excl;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+}
 
 // Decoupled look-back for one digit: sum the counts of the predecessors of tile t back to
 // the nearest one that has published an inclusive prefix.  kLookWin status words are read
@@ -335,13 +388,14 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
         const uint32_t* hist = a.hist + (size_t)k * a.hist_stride;
         const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;  // wave w owns a contiguous slice
 
-        // ---- whole records into registers (all loads in flight at once), then the digit
+        // ---- key modes first: the tile's digit counts are published as early as possible;
+        // the other arrays are loaded while the look-back waits on the predecessors
         CT c[R][ITEMS];
         VT v[ITEMS];
         uint32_t dg[ITEMS], lp[ITEMS];
 #pragma unroll
-        for (int m = 0; m < R; ++m) load_items<CT, ITEMS>((const CT*)a.src_crd[m], start, len, wb, c[m]);
-        load_items<VT, ITEMS>((const VT*)a.src_val, start, len, wb, v);
+        for (int m = 0; m < R; ++m)
+            if (a.key.mask[m]) load_items<CT, ITEMS>((const CT*)a.src_crd[m], start, len, wb, c[m]);
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             uint64_t key = 0;
@@ -384,6 +438,11 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
             const uint32_t tcnt = run;
             uint32_t* st = a.status + (size_t)t * kBins;
             st_status(&st[b], (first ? kFlagP : kFlagA) | tcnt);
+            // the rest of the records, in flight during the scans and the look-back
+#pragma unroll
+            for (int m = 0; m < R; ++m)
+                if (!a.key.mask[m]) load_items<CT, ITEMS>((const CT*)a.src_crd[m], start, len, wb, c[m]);
+            load_items<VT, ITEMS>((const VT*)a.src_val, start, len, wb, v);
             const uint32_t tstart = block_excl_scan(tcnt, s_tmp, nullptr);
             const uint32_t hstart = block_excl_scan(hist[b], s_tmp + kWaves, nullptr);
             uint32_t excl = 0;
@@ -450,56 +509,45 @@ __global__ void __launch_bounds__(256) k_boundary(BoundArgs a) {
     const uint32_t len = min((uint32_t)kBoundTile, a.n - start);
     const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
     uint64_t flags[ITEMS];
+    bool f[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) f[i] = (start + wb + i * 64 == 0);
+    for (int j = 0; j < a.nprefix; ++j) {  // all loads of one prefix mode in flight together
+        const CT* p = (const CT*)a.crd[a.prefix[j]];
+        CT cur[ITEMS], prv[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t off = wb + i * 64;
+            const uint32_t e = start + off;
+            const bool ok = off < len && e > 0;
+            cur[i] = ok ? p[e] : CT(0);
+            prv[i] = ok ? p[e - 1] : CT(0);
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) f[i] |= cur[i] != prv[i];
+    }
     uint32_t wcount = 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t off = wb + i * 64;
-        const uint32_t e = start + off;
-        bool f = false;
-        if (off < len) {
-            f = (e == 0);
-            for (int j = 0; j < a.nprefix && !f; ++j) {
-                const CT* p = (const CT*)a.crd[a.prefix[j]];
-                f = p[e] != p[e - 1];
-            }
-        }
-        flags[i] = ballot(f);
+        flags[i] = ballot(f[i] && (wb + i * 64 < len));
         wcount += (uint32_t)__popcll(flags[i]);
     }
     if (lane == 0) s_wsum[wave] = wcount;
     __syncthreads();
-    if (tid == 0) {
+    if (wave == 0) {
         uint32_t tot = 0;
         for (int w = 0; w < kWaves; ++w) tot += s_wsum[w];
         uint32_t* st = a.status + t;
-        uint32_t excl = 0;
-        if (t == 0) {
-            st_status(st, kFlagP | tot);
-        } else {
-            st_status(st, kFlagA | tot);
-            uint32_t j = t - 1, spins = 0;
-            for (;;) {
-                const uint32_t w = ld_status(&a.status[j]);
-                const uint32_t f = w & ~kCntMask;
-                if (f == 0) {
-                    if (++spins > kSpinLimit) {
-                        atomicOr(a.err, 1u);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                excl += w & kCntMask;
-                if (f == kFlagP) break;
-                --j;
+        if (lane == 0) st_status(st, (t == 0 ? kFlagP : kFlagA) | tot);
+        const uint32_t excl = t == 0 ? 0u : wave_look_back(a.status, t, 1, 0, 0, a.err);
+        if (lane == 0) {
+            if (t != 0) st_status(st, kFlagP | (excl + tot));
+            s_geo[1] = excl;
+            if (start + len == a.n) {
+                *a.nb_out = excl + tot;
+                a.seg_start[excl + tot] = a.n;
+                a.region_seg[(a.n + kRegion - 1) / kRegion] = excl + tot;
             }
-            st_status(st, kFlagP | (excl + tot));
-        }
-        s_geo[1] = excl;
-        if (start + len == a.n) {
-            *a.nb_out = excl + tot;
-            a.seg_start[excl + tot] = a.n;
-            a.region_seg[(a.n + kRegion - 1) / kRegion] = excl + tot;
         }
     }
     __syncthreads();
@@ -547,8 +595,10 @@ __global__ void __launch_bounds__(256) k_classify(ClassArgs a) {
 
 // Stable sort of short runs of records entirely in LDS, by (segment number, group key).
 // Work items: the tiny segments starting in each region of kRegion records (their union
-// is one run of fewer than kSmallCap records), then every medium segment.
-template <typename CT, typename VT>
+// is one run of fewer than kSmallCap records), then every medium segment.  A run's records
+// are loaded into registers right away (all loads in flight at once), sorted through LDS
+// by LSD passes over the key bits that vary inside the run, and written back in place.
+template <int R, typename CT, typename VT>
 __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
     constexpr int CAP = kSmallCap, ITEMS = CAP / kBlock;
     __shared__ uint64_t s_key[CAP];   // keys, then staging of each array
@@ -577,7 +627,6 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
                 const uint2 md = a.med[item - a.nregions];
                 rs = md.x;
                 re = md.x + md.y;
-                sa = se = 0;
             }
             s_run[0] = rs;
             s_run[1] = re;
@@ -585,18 +634,52 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
             s_run[3] = se;
         }
         __syncthreads();
-        const uint32_t rs = s_run[0], L = s_run[1] - s_run[0];
-        const uint32_t sa = s_run[2], se = s_run[3];
+        const uint32_t rs = __builtin_amdgcn_readfirstlane(s_run[0]);
+        const uint32_t L = __builtin_amdgcn_readfirstlane(s_run[1]) - rs;
+        const uint32_t sa = __builtin_amdgcn_readfirstlane(s_run[2]);
+        const uint32_t se = __builtin_amdgcn_readfirstlane(s_run[3]);
         if (L == 0) {
             __syncthreads();
             continue;
         }
         const bool region = item < a.nregions;
+
+        // ---- the whole run into registers: slot j = i*kBlock + tid
+        CT c[R][ITEMS];
+        VT v[ITEMS];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const CT* src = (const CT*)a.src_crd[m] + rs;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t j = i * kBlock + tid;
+                c[m][i] = j < L ? src[j] : CT(0);
+            }
+        }
+        {
+            const VT* src = (const VT*)a.src_val + rs;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t j = i * kBlock + tid;
+                v[i] = j < L ? src[j] : VT(0);
+            }
+        }
+
         // ---- segment number of every record of the run
-        for (uint32_t j = tid; j < L; j += kBlock) s_seg[j] = 0;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) s_seg[i * kBlock + tid] = 0;
         __syncthreads();
-        if (region)
-            for (uint32_t s = sa + 1 + tid; s < se; s += kBlock) s_seg[a.seg_start[s] - rs] = 1;
+        if (region) {
+            uint32_t st[ITEMS / 2];
+#pragma unroll
+            for (int i = 0; i < ITEMS / 2; ++i) {  // at most kRegion segments start in a region
+                const uint32_t s2 = sa + 1 + i * kBlock + tid;
+                st[i] = s2 < se ? a.seg_start[s2] : 0xFFFFFFFFu;
+            }
+#pragma unroll
+            for (int i = 0; i < ITEMS / 2; ++i)
+                if (st[i] != 0xFFFFFFFFu) s_seg[st[i] - rs] = 1;
+        }
         __syncthreads();
         {
             // blocked inclusive scan: thread tid owns slots [tid*ITEMS, tid*ITEMS+ITEMS)
@@ -615,16 +698,22 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
             }
         }
         __syncthreads();
-        // ---- composite keys: (segment number << 52) | group key
+        // ---- composite keys: (segment number << key bits) | group key
         uint64_t kor = 0, kand = ~0ull;
-        for (uint32_t j = tid; j < L; j += kBlock) {
-            CT c[8];
-            for (int m = 0; m < a.r; ++m) c[m] = a.key.mask[m] ? ((const CT*)a.src_crd[m])[rs + j] : CT(0);
-            const uint64_t key = compose_key<CT>(c, a.key, a.r) | ((uint64_t)s_seg[j] << 52);
-            s_key[j] = key;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = i * kBlock + tid;
+            if (j < L) {
+                uint64_t key = 0;
+#pragma unroll
+                for (int m = 0; m < R; ++m)
+                    if (a.key.mask[m]) key |= (((uint64_t)c[m][i] >> a.key.src_lo[m]) & a.key.mask[m]) << a.key.dst[m];
+                key |= (uint64_t)s_seg[j] << a.key_bits;
+                s_key[j] = key;
+                kor |= key;
+                kand &= key;
+            }
             s_ia[j] = (uint16_t)j;
-            kor |= key;
-            kand &= key;
         }
         for (int o = 32; o > 0; o >>= 1) {
             kor |= __shfl_xor(kor, o, 64);
@@ -637,6 +726,7 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
         __syncthreads();
         kor = 0;
         kand = ~0ull;
+#pragma unroll
         for (int w = 0; w < kWaves; ++w) {
             kor |= s_red[w];
             kand &= s_red[kWaves + w];
@@ -650,6 +740,7 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
             for (int sh = lo; sh <= hi; sh += 8) {
                 const int nbits = min(8, hi - sh + 1);
                 const uint32_t dmask = (1u << nbits) - 1u;
+                if (((vary >> sh) & dmask) == 0) continue;  // digit constant over the run
                 for (int b = lane; b < kBins; b += 64) s_cnt[wave * kBins + b] = 0;
                 uint32_t dg[ITEMS], lp[ITEMS];
                 uint16_t sv[ITEMS];
@@ -703,23 +794,35 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
                 nxt = t;
             }
         }
-        // ---- move every array: stage the run in LDS, write it out in sorted order
-        for (int m = 0; m <= a.r; ++m) {
-            const bool isv = (m == a.r);
+        // ---- write every array back in sorted order: stage by original slot, gather by perm
+        uint16_t pm[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) pm[i] = cur[i * kBlock + tid];
+#pragma unroll
+        for (int m = 0; m <= R; ++m) {
             __syncthreads();
-            if ((isv ? sizeof(VT) : sizeof(CT)) == 8) {
-                const uint64_t* src = (const uint64_t*)(isv ? a.src_val : a.src_crd[m]) + rs;
-                uint64_t* dst = (uint64_t*)(isv ? a.dst_val : a.dst_crd[m]) + rs;
-                for (uint32_t j = tid; j < L; j += kBlock) s_key[j] = src[j];
+            if (m < R) {
+                CT* st = (CT*)s_key;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) st[i * kBlock + tid] = c[m][i];
                 __syncthreads();
-                for (uint32_t j = tid; j < L; j += kBlock) dst[j] = s_key[cur[j]];
+                CT* dst = (CT*)a.dst_crd[m] + rs;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t j = i * kBlock + tid;
+                    if (j < L) dst[j] = st[pm[i]];
+                }
             } else {
-                const uint32_t* src = (const uint32_t*)(isv ? a.src_val : a.src_crd[m]) + rs;
-                uint32_t* dst = (uint32_t*)(isv ? a.dst_val : a.dst_crd[m]) + rs;
-                uint32_t* st = (uint32_t*)s_key;
-                for (uint32_t j = tid; j < L; j += kBlock) st[j] = src[j];
+                VT* st = (VT*)s_key;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) st[i * kBlock + tid] = v[i];
                 __syncthreads();
-                for (uint32_t j = tid; j < L; j += kBlock) dst[j] = st[cur[j]];
+                VT* dst = (VT*)a.dst_val + rs;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t j = i * kBlock + tid;
+                    if (j < L) dst[j] = st[pm[i]];
+                }
             }
         }
         __syncthreads();
@@ -775,24 +878,28 @@ __global__ void __launch_bounds__(256) k_csf(CsfArgs a) {
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t off = wb + i * 64;
-        const uint32_t e = start + off;
-        int lv = a.r;  // no difference within levels 1..r-1
-        if (off < len) {
-            if (e == 0) {
-                lv = 0;
-            } else {
-                for (int d = 0; d < L; ++d) {
-                    const CT* p = (const CT*)a.crd[a.sigma[d]];
-                    if (p[e] != p[e - 1]) {
-                        lv = d;
-                        break;
-                    }
-                }
-            }
-        } else {
-            lv = 0xFF;
+        // lev: first level whose mode differs from the previous record (r: none below r)
+        lev[i] = off < len ? (start + off == 0 ? 0 : (uint8_t)a.r) : 0xFF;
+    }
+    for (int d = L - 1; d >= 0; --d) {  // deepest level first, so the shallowest wins
+        const CT* p = (const CT*)a.crd[a.sigma[d]];
+        CT cur[ITEMS], prv[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t off = wb + i * 64;
+            const uint32_t e = start + off;
+            const bool ok = off < len && e > 0;
+            cur[i] = ok ? p[e] : CT(0);
+            prv[i] = ok ? p[e - 1] : CT(0);
         }
-        lev[i] = (uint8_t)lv;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (lev[i] != 0xFF && lev[i] != 0 && cur[i] != prv[i]) lev[i] = (uint8_t)d;
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t off = wb + i * 64;
+        const int lv = lev[i];
         for (int d = 0; d < L; ++d) wcnt[d] += (uint32_t)__popcll(ballot(off < len && lv <= d));
     }
     if (lane == 0)
@@ -995,18 +1102,26 @@ hipError_t launch_classify(const ClassArgs& a, uint32_t max_segments, hipStream_
     return hipGetLastError();
 }
 
+template <typename CT, typename VT>
+hipError_t small_cv(const SmallArgs& a, uint32_t grid, hipStream_t s) {
+#define QSD_SMALL_CASE(RR) \
+    case RR: hipLaunchKernelGGL((k_small<RR, CT, VT>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    switch (a.r) {
+        QSD_SMALL_CASE(1) QSD_SMALL_CASE(2) QSD_SMALL_CASE(3) QSD_SMALL_CASE(4)
+        QSD_SMALL_CASE(5) QSD_SMALL_CASE(6) QSD_SMALL_CASE(7) QSD_SMALL_CASE(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef QSD_SMALL_CASE
+    return hipGetLastError();
+}
+
 hipError_t launch_small(const SmallArgs& a, int crd_bytes, int val_bytes, uint32_t max_items, hipStream_t s) {
     if (!max_items) return hipSuccess;
     const int cu = device_cu_count();
     const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(max_items, (uint32_t)cu * 8));
-    if (crd_bytes == 8) {
-        if (val_bytes == 8) hipLaunchKernelGGL((k_small<uint64_t, uint64_t>), dim3(grid), dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((k_small<uint64_t, uint32_t>), dim3(grid), dim3(kBlock), 0, s, a);
-    } else {
-        if (val_bytes == 8) hipLaunchKernelGGL((k_small<uint32_t, uint64_t>), dim3(grid), dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((k_small<uint32_t, uint32_t>), dim3(grid), dim3(kBlock), 0, s, a);
-    }
-    return hipGetLastError();
+    if (crd_bytes == 8)
+        return val_bytes == 8 ? small_cv<uint64_t, uint64_t>(a, grid, s) : small_cv<uint64_t, uint32_t>(a, grid, s);
+    return val_bytes == 8 ? small_cv<uint32_t, uint64_t>(a, grid, s) : small_cv<uint32_t, uint32_t>(a, grid, s);
 }
 
 hipError_t launch_validate(const ValidateArgs& a, int crd_bytes, hipStream_t s) {
