@@ -124,6 +124,62 @@ qsd_status qsd_pack_csf(qsd_plan_t plan, int64_t nnz, const void* const* sorted_
                         void* const* pos, void* const* crd, int64_t* fiber_counts,
                         void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Batched transposition: many independent tensors (uneven nnz, orders and mode orders) in a
+ * handful of kernel launches that can be captured into one HIP graph.  All tensors of a batch
+ * share the coordinate and value types.  Each tensor is sorted stably by its flattened key
+ * (sigma_1..sigma_q, where sigma_{q+1}..sigma_r is the longest tail already in input order),
+ * which yields the same output as every schedule of qsd_plan.  Tensors with at most
+ * `small_cap` nonzeros are sorted whole in LDS by one workgroup; the others take global
+ * digit passes, launch p running the p-th pass of every tensor that has one.
+ *
+ * Use: qsd_batch_plan -> qsd_batch_workspace -> qsd_batch_bind (uploads the per-tensor
+ * pointer tables into the workspace; synchronises the stream) -> qsd_batch_transpose (kernel
+ * launches only: no allocation, no host synchronisation, graph-capturable) any number of
+ * times.  Re-bind after changing buffers or tuning.  qsd_batch_tune times candidate settings
+ * (items per thread, digit width, small-tensor cutoff) on the bound buffers and keeps the
+ * fastest; it overwrites the outputs.
+ * --------------------------------------------------------------------------------------- */
+typedef struct qsd_batch_s* qsd_batch_t;
+
+typedef struct qsd_batch_io {
+    const void* in_crd[QSD_MAX_ORDER];  /* device pointers, mode order */
+    const void* in_val;
+    void* out_crd[QSD_MAX_ORDER];
+    void* out_val;
+} qsd_batch_io;
+
+typedef struct qsd_tuning {
+    int32_t items;       /* records per thread in a digit pass: 8 or 16 (0 = automatic) */
+    int32_t radix_bits;  /* digit width of a pass: 4..8 */
+    int32_t small_cap;   /* tensors with nnz <= small_cap are sorted in LDS: 0..4096 */
+} qsd_tuning;
+
+/* descs: count descriptors (flags ignored).  Returns QSD_ERR_UNSUPPORTED for mixed types, a
+ * flattened key wider than 128 bits, or more than 16 digit passes for one tensor. */
+qsd_status qsd_batch_plan(const qsd_desc* descs, int32_t count, qsd_batch_t* out);
+void qsd_batch_destroy(qsd_batch_t batch);
+qsd_status qsd_batch_set_tuning(qsd_batch_t batch, const qsd_tuning* tuning);
+qsd_status qsd_batch_get_tuning(qsd_batch_t batch, qsd_tuning* tuning);
+qsd_status qsd_batch_workspace(qsd_batch_t batch, size_t* bytes);
+/* io: host array of `count` entries (device pointers).  Copies the tables into ws. */
+qsd_status qsd_batch_bind(qsd_batch_t batch, const qsd_batch_io* io, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
+qsd_status qsd_batch_transpose(qsd_batch_t batch, void* ws, size_t ws_bytes, hipStream_t stream);
+/* Autotuner: tries items {8, 16} x radix bits {6, 7, 8} x small_cap {0, 1024, 4096}, `reps`
+ * timed runs each (best of), on the bound buffers; applies and returns the fastest setting and
+ * its time.  ws must be large enough for every candidate (qsd_batch_workspace_max). */
+qsd_status qsd_batch_workspace_max(qsd_batch_t batch, size_t* bytes);
+qsd_status qsd_batch_tune(qsd_batch_t batch, const qsd_batch_io* io, void* ws, size_t ws_bytes,
+                          hipStream_t stream, int32_t reps, qsd_tuning* best, float* best_ms);
+
+/* HIP graph of qsd_batch_transpose on the bound workspace: captured on an internal stream and
+ * instantiated; launch it on any stream.  The graph holds the buffer addresses bound now. */
+typedef struct qsd_graph_s* qsd_graph_t;
+qsd_status qsd_batch_graph(qsd_batch_t batch, void* ws, size_t ws_bytes, qsd_graph_t* out);
+qsd_status qsd_graph_launch(qsd_graph_t graph, hipStream_t stream);
+void qsd_graph_destroy(qsd_graph_t graph);
+
 /* Device-side status of the last call that used this workspace: 0 when every kernel ran
  * normally, otherwise a bit set (1: a bounded wait in a scan timed out).  Synchronises
  * `stream` and reads 4 bytes.  Validation results are returned by qsd_transpose itself. */
@@ -137,7 +193,8 @@ const char* qsd_status_str(qsd_status s);
  * entry per kernel kind: launches, summed event durations, and the algorithmic bytes the
  * launches had to move (the data-movement model of the kind; 0 where none is modelled).
  * Kinds: zero, copy, validate, hist, digit, boundary, classify, small, hist_seg,
- * digit_seg, csf.  Recording adds two event records per launch; it is off by default. */
+ * digit_seg, csf, hist_batch, small_batch, digit_batch.  Launches made while the stream is
+ * being captured into a graph are not recorded.  Recording adds two event records per launch; it is off by default. */
 typedef struct qsd_kernel_stat {
     char name[24];
     int64_t launches;

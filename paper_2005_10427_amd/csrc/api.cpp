@@ -150,9 +150,11 @@ struct Bufs {
 };
 
 // ---- launch timing (qsd_profile_*)
-enum Kind { kZero, kCopy, kValidate, kHist, kDigit, kBoundary, kClassify, kSmall, kHistSeg, kDigitSeg, kCsf, kNumKinds };
+enum Kind { kZero, kCopy, kValidate, kHist, kDigit, kBoundary, kClassify, kSmall, kHistSeg, kDigitSeg, kCsf,
+            kHistBatch, kSmallBatch, kDigitBatch, kNumKinds };
 const char* kKindName[kNumKinds] = {"zero", "copy", "validate", "hist", "digit", "boundary",
-                                    "classify", "small", "hist_seg", "digit_seg", "csf"};
+                                    "classify", "small", "hist_seg", "digit_seg", "csf",
+                                    "hist_batch", "small_batch", "digit_batch"};
 struct ProfRec {
     int kind;
     hipEvent_t a, b;
@@ -177,6 +179,8 @@ hipEvent_t pool_event() {
 template <typename F>
 hipError_t timed(int kind, double bytes, hipStream_t s, F&& fn) {
     if (!g_prof_on) return fn();
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return fn();
     std::lock_guard<std::mutex> lk(g_prof_mu);
     ProfRec r{kind, pool_event(), pool_event(), bytes};
     if (r.a) hipEventRecord(r.a, s);
@@ -645,6 +649,483 @@ qsd_status qsd_pack_csf(qsd_plan_t plan, int64_t nnz, const void* const* sorted_
     ca.err = ctl + kCtlErr;
     if (timed(kCsf, 0, stream, [&] { return launch_csf(ca, p.crd_bytes, stream); }) != hipSuccess) return QSD_ERR_HIP;
     return QSD_OK;
+}
+
+}  // extern "C"
+
+// =========================================================================================
+// Batched transposition
+// =========================================================================================
+namespace {
+
+DevKey dev_key(const KeySpec& ks, int r) {
+    DevKey k{};
+    for (int m = 0; m < r; ++m) {
+        k.mask[m] = ks.width[m] ? ((ks.width[m] >= 64) ? ~0ull : ((1ull << ks.width[m]) - 1)) : 0;
+        k.src_lo[m] = ks.src_lo[m];
+        k.dst[m] = ks.dst[m];
+    }
+    return k;
+}
+
+struct BTensor {
+    int r = 0;
+    uint32_t n = 0;
+    int bits[kMaxR] = {};
+    int in_order[kMaxR] = {}, out_order[kMaxR] = {};
+    std::vector<int> keys;       // flattened key, most significant first
+    std::vector<SubKey> subs;    // least significant first
+    int D = 0;                   // digit passes
+    bool small = false;
+    uint32_t tile0 = 0, tiles = 0;
+    size_t rec_off = 0;          // workspace record area (large tensors)
+    size_t hist_word = 0;        // first histogram word (large tensors)
+};
+
+}  // namespace
+
+struct qsd_batch_s {
+    int crd_bytes = 4, val_bytes = 8, rmax = 1;
+    qsd_tuning tun{0, 8, kSmallCap};
+    std::vector<BTensor> t;
+    // derived from the tuning
+    int items = 16, tile = 4096, maxD = 0;
+    uint32_t total_tiles = 0;
+    std::vector<int> large, small;                 // tensor indices
+    std::vector<std::vector<uint32_t>> launch_tiles;  // per launch: stable tile ids
+    size_t hist_words = 0;
+    // workspace layout
+    size_t off_ctl = 0, off_rec = 0, off_hist = 0, off_status[2] = {0, 0}, off_tab = 0, total = 0;
+    size_t tab_pass = 0, tab_map = 0, tab_job = 0, tab_hjob = 0, tab_sjob = 0, tab_bytes = 0;
+    std::vector<size_t> map_off;                   // per launch, word offset in the map table
+    // bound host tables
+    std::vector<char> host_tab;
+    bool bound = false;
+    void* bound_ws = nullptr;
+};
+
+struct qsd_graph_s {
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+size_t rec_bytes(const qsd_batch_s* b, int r) { return (size_t)r * b->crd_bytes + b->val_bytes; }
+
+qsd_status batch_derive(qsd_batch_s* b) {
+    const qsd_tuning& tu = b->tun;
+    b->items = digit_items(b->rmax, b->crd_bytes, b->val_bytes, tu.items);
+    b->tile = kBlock * b->items;
+    b->large.clear();
+    b->small.clear();
+    b->maxD = 0;
+    b->total_tiles = 0;
+    b->hist_words = 0;
+    size_t rec = 0;
+    for (size_t i = 0; i < b->t.size(); ++i) {
+        BTensor& x = b->t[i];
+        x.subs = make_subkeys(x.keys, x.bits, tu.radix_bits);
+        x.D = 0;
+        for (auto& sk : x.subs) x.D += (int)sk.passes.size();
+        if (x.subs.size() > 2 || x.D > 16) return QSD_ERR_UNSUPPORTED;
+        x.small = x.n <= (uint32_t)tu.small_cap;
+        if (x.n == 0) continue;
+        if (x.small) {
+            b->small.push_back((int)i);
+            continue;
+        }
+        if (x.D == 0) {  // identity: one zero-width pass copies the records stably
+            SubKey sk{};
+            std::memset(&sk.key, 0, sizeof(sk.key));
+            sk.passes.push_back(PassSpec{0, 0});
+            x.subs.assign(1, sk);
+            x.D = 1;
+        }
+        b->large.push_back((int)i);
+        x.tile0 = b->total_tiles;
+        x.tiles = (x.n + b->tile - 1) / b->tile;
+        b->total_tiles += x.tiles;
+        x.hist_word = b->hist_words;
+        b->hist_words += (size_t)x.D * kBins;
+        x.rec_off = rec;
+        for (int m = 0; m <= x.r; ++m) rec = up(rec + (size_t)x.n * (m < x.r ? b->crd_bytes : b->val_bytes));
+        b->maxD = std::max(b->maxD, x.D);
+    }
+    b->launch_tiles.assign(b->maxD, {});
+    for (int p = 0; p < b->maxD; ++p)
+        for (int i : b->large)
+            if (p < b->t[i].D)
+                for (uint32_t k = 0; k < b->t[i].tiles; ++k) b->launch_tiles[p].push_back(b->t[i].tile0 + k);
+    // layout
+    size_t at = 0;
+    b->off_ctl = at;
+    at = up(at + kCtlWords * 4);
+    b->off_rec = at;
+    at = up(at + rec);
+    b->off_hist = at;
+    at = up(at + b->hist_words * 4);
+    for (int k = 0; k < 2; ++k) {
+        b->off_status[k] = at;
+        at = up(at + (size_t)b->total_tiles * kBins * 4);
+    }
+    const size_t nl = b->large.size();
+    b->off_tab = at;
+    size_t tb = 0;
+    b->tab_pass = tb;
+    tb = up(tb + (size_t)b->maxD * nl * sizeof(BatchPass));
+    b->tab_map = tb;
+    b->map_off.assign(b->maxD, 0);
+    size_t words = 0;
+    for (int p = 0; p < b->maxD; ++p) {
+        b->map_off[p] = words;
+        words += b->launch_tiles[p].size();
+    }
+    tb = up(tb + words * 4);
+    b->tab_job = tb;
+    tb = up(tb + (size_t)b->total_tiles * 4);
+    b->tab_hjob = tb;
+    tb = up(tb + nl * sizeof(BatchHistJob));
+    b->tab_sjob = tb;
+    tb = up(tb + b->small.size() * sizeof(BatchSmallJob));
+    b->tab_bytes = tb;
+    at = up(at + tb);
+    b->total = at;
+    b->bound = false;
+    return QSD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qsd_status qsd_batch_plan(const qsd_desc* descs, int32_t count, qsd_batch_t* out) {
+    if (!out || (!descs && count > 0)) return QSD_ERR_NULL;
+    *out = nullptr;
+    if (count < 0) return QSD_ERR_TOO_LARGE;
+    auto* b = new qsd_batch_s();
+    for (int i = 0; i < count; ++i) {
+        const qsd_status st = check_desc(&descs[i]);
+        if (st != QSD_OK) {
+            delete b;
+            return st;
+        }
+        const int cb = descs[i].crd_type == QSD_I64 ? 8 : 4, vb = descs[i].val_type == QSD_F64 ? 8 : 4;
+        if (i == 0) {
+            b->crd_bytes = cb;
+            b->val_bytes = vb;
+        } else if (cb != b->crd_bytes || vb != b->val_bytes) {
+            delete b;
+            return QSD_ERR_UNSUPPORTED;
+        }
+        BTensor x;
+        x.r = descs[i].order;
+        x.n = (uint32_t)descs[i].nnz;
+        for (int m = 0; m < x.r; ++m) {
+            x.bits[m] = bits_for_extent(descs[i].extents[m]);
+            x.in_order[m] = descs[i].in_order[m];
+            x.out_order[m] = descs[i].out_order[m];
+        }
+        x.keys = flattened_key(x.r, x.in_order, x.out_order, x.bits);
+        b->rmax = std::max(b->rmax, x.r);
+        b->t.push_back(x);
+    }
+    const qsd_status st = batch_derive(b);
+    if (st != QSD_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return QSD_OK;
+}
+
+void qsd_batch_destroy(qsd_batch_t b) { delete b; }
+
+qsd_status qsd_batch_set_tuning(qsd_batch_t b, const qsd_tuning* tu) {
+    if (!b || !tu) return QSD_ERR_NULL;
+    if ((tu->items != 0 && tu->items != 8 && tu->items != 16) || tu->radix_bits < 4 || tu->radix_bits > 8 ||
+        tu->small_cap < 0 || tu->small_cap > kSmallCap)
+        return QSD_ERR_UNSUPPORTED;
+    const qsd_tuning old = b->tun;
+    b->tun = *tu;
+    const qsd_status st = batch_derive(b);
+    if (st != QSD_OK) {
+        b->tun = old;
+        batch_derive(b);
+    }
+    return st;
+}
+
+qsd_status qsd_batch_get_tuning(qsd_batch_t b, qsd_tuning* tu) {
+    if (!b || !tu) return QSD_ERR_NULL;
+    *tu = b->tun;
+    tu->items = b->items;
+    return QSD_OK;
+}
+
+qsd_status qsd_batch_workspace(qsd_batch_t b, size_t* bytes) {
+    if (!b || !bytes) return QSD_ERR_NULL;
+    *bytes = b->total;
+    return QSD_OK;
+}
+
+qsd_status qsd_batch_workspace_max(qsd_batch_t b, size_t* bytes) {
+    if (!b || !bytes) return QSD_ERR_NULL;
+    const qsd_tuning keep = b->tun;
+    size_t mx = 0;
+    for (int items : {8, 16})
+        for (int rb : {6, 7, 8})
+            for (int cap : {0, 1024, kSmallCap}) {
+                b->tun = qsd_tuning{items, rb, cap};
+                if (batch_derive(b) == QSD_OK) mx = std::max(mx, b->total);
+            }
+    b->tun = keep;
+    batch_derive(b);
+    *bytes = mx;
+    return QSD_OK;
+}
+
+qsd_status qsd_batch_bind(qsd_batch_t b, const qsd_batch_io* io, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!b || (!io && !b->t.empty())) return QSD_ERR_NULL;
+    if (!ws || ws_bytes < b->total) return QSD_ERR_WORKSPACE;
+    char* W = (char*)ws;
+    b->host_tab.assign(b->tab_bytes, 0);
+    char* H = b->host_tab.data();
+    const size_t nl = b->large.size();
+    // per-launch pass tables of the large tensors
+    for (int p = 0; p < b->maxD; ++p) {
+        for (size_t li = 0; li < nl; ++li) {
+            const BTensor& x = b->t[b->large[li]];
+            const qsd_batch_io& q = io[b->large[li]];
+            BatchPass& e = ((BatchPass*)(H + b->tab_pass))[(size_t)p * nl + li];
+            std::memset(&e, 0, sizeof(e));
+            e.active = p < x.D;
+            e.r = x.r;
+            e.n = x.n;
+            e.tile0 = x.tile0;
+            if (!e.active) continue;
+            // hop p writes OUT when (D-1-p) is even, else the tensor's workspace records
+            auto buf = [&](int hop, int m) -> void* {
+                const bool to_out = ((x.D - 1 - hop) % 2) == 0;
+                if (to_out) return m < x.r ? q.out_crd[m] : q.out_val;
+                size_t off = x.rec_off;
+                for (int k = 0; k < m; ++k) off = up(off + (size_t)x.n * b->crd_bytes);
+                return W + b->off_rec + off;
+            };
+            for (int m = 0; m <= x.r; ++m) {
+                const void* src = p == 0 ? (m < x.r ? q.in_crd[m] : q.in_val) : buf(p - 1, m);
+                void* dst = buf(p, m);
+                if (m < x.r) {
+                    e.src_crd[m] = src;
+                    e.dst_crd[m] = dst;
+                } else {
+                    e.src_val = src;
+                    e.dst_val = dst;
+                }
+            }
+            int k = p, sub = 0;
+            while (k >= (int)x.subs[sub].passes.size()) k -= (int)x.subs[sub++].passes.size();
+            e.key = dev_key(x.subs[sub].key, x.r);
+            e.lo = x.subs[sub].passes[k].lo;
+            e.bits = x.subs[sub].passes[k].bits;
+            e.hist = (const uint32_t*)(W + b->off_hist) + x.hist_word + (size_t)p * kBins;
+        }
+        uint32_t* map = (uint32_t*)(H + b->tab_map) + b->map_off[p];
+        std::copy(b->launch_tiles[p].begin(), b->launch_tiles[p].end(), map);
+    }
+    uint32_t* tj = (uint32_t*)(H + b->tab_job);
+    BatchHistJob* hj = (BatchHistJob*)(H + b->tab_hjob);
+    for (size_t li = 0; li < nl; ++li) {
+        const BTensor& x = b->t[b->large[li]];
+        for (uint32_t k = 0; k < x.tiles; ++k) tj[x.tile0 + k] = (uint32_t)li;
+        BatchHistJob& j = hj[li];
+        std::memset(&j, 0, sizeof(j));
+        for (int m = 0; m < x.r; ++m) j.crd[m] = io[b->large[li]].in_crd[m];
+        j.r = x.r;
+        j.nsub = (int)x.subs.size();
+        int pidx = 0;
+        for (int sidx = 0; sidx < j.nsub; ++sidx) {
+            j.key[sidx] = dev_key(x.subs[sidx].key, x.r);
+            for (const auto& ps : x.subs[sidx].passes) {
+                j.lo[pidx] = ps.lo;
+                j.bits[pidx] = ps.bits;
+                j.sub[pidx] = sidx;
+                ++pidx;
+            }
+        }
+        j.npass = pidx;
+        j.n = x.n;
+        j.tile0 = x.tile0;
+        j.hist = (uint32_t*)(W + b->off_hist) + x.hist_word;
+    }
+    BatchSmallJob* sj = (BatchSmallJob*)(H + b->tab_sjob);
+    for (size_t si = 0; si < b->small.size(); ++si) {
+        const BTensor& x = b->t[b->small[si]];
+        const qsd_batch_io& q = io[b->small[si]];
+        BatchSmallJob& j = sj[si];
+        std::memset(&j, 0, sizeof(j));
+        for (int m = 0; m < x.r; ++m) {
+            j.src_crd[m] = q.in_crd[m];
+            j.dst_crd[m] = q.out_crd[m];
+        }
+        j.src_val = q.in_val;
+        j.dst_val = q.out_val;
+        j.nsub = (int)x.subs.size();
+        for (int sidx = 0; sidx < j.nsub; ++sidx) {
+            j.key[sidx] = dev_key(x.subs[sidx].key, x.r);
+            j.key_bits[sidx] = x.subs[sidx].key.bits;
+        }
+        j.r = x.r;
+        j.n = x.n;
+    }
+    if (b->tab_bytes) {
+        if (hipMemcpyAsync(W + b->off_tab, H, b->tab_bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+            return QSD_ERR_HIP;
+        if (hipStreamSynchronize(stream) != hipSuccess) return QSD_ERR_HIP;
+    }
+    b->bound = true;
+    b->bound_ws = ws;
+    return QSD_OK;
+}
+
+qsd_status qsd_batch_transpose(qsd_batch_t b, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!b) return QSD_ERR_NULL;
+    if (!ws || ws_bytes < b->total || !b->bound || ws != b->bound_ws) return QSD_ERR_WORKSPACE;
+    char* W = (char*)ws;
+    uint32_t* ctl = (uint32_t*)(W + b->off_ctl);
+    uint32_t* S[2] = {(uint32_t*)(W + b->off_status[0]), (uint32_t*)(W + b->off_status[1])};
+    const char* T = W + b->off_tab;
+    hipError_t e;
+#define QSD_CK(x)                                        \
+    do {                                                 \
+        if ((e = (x)) != hipSuccess) return QSD_ERR_HIP; \
+    } while (0)
+    ZeroArgs z{};
+    z.ptr[0] = ctl;
+    z.words[0] = kCtlWords;
+    if (b->hist_words) {
+        z.ptr[1] = (uint32_t*)(W + b->off_hist);
+        z.words[1] = b->hist_words;
+    }
+    QSD_CK(timed(kZero, 0, stream, [&] { return launch_zero(z, stream); }));
+    if (!b->large.empty()) {
+        BatchHistArgs ha{};
+        ha.jobs = (const BatchHistJob*)(T + b->tab_hjob);
+        ha.tile_job = (const uint32_t*)(T + b->tab_job);
+        ha.ntiles = b->total_tiles;
+        ha.tile = (uint32_t)b->tile;
+        ha.status_zero = S[0];
+        const int grid = (int)std::max<uint32_t>(1, std::min<uint32_t>(b->total_tiles, (uint32_t)device_cu_count() * 4));
+        QSD_CK(timed(kHistBatch, 0, stream, [&] { return launch_hist_batch(ha, b->rmax, b->crd_bytes, grid, stream); }));
+    }
+    if (!b->small.empty()) {
+        const auto* jobs = (const BatchSmallJob*)(T + b->tab_sjob);
+        const uint32_t nj = (uint32_t)b->small.size();
+        QSD_CK(timed(kSmallBatch, 0, stream,
+                     [&] { return launch_small_batch(jobs, nj, b->rmax, b->crd_bytes, b->val_bytes, stream); }));
+    }
+    const size_t nl = b->large.size();
+    for (int p = 0; p < b->maxD; ++p) {
+        DigitArgs da{};
+        da.seg_mode = 2;
+        da.ntiles = (uint32_t)b->launch_tiles[p].size();
+        da.tile_map = (const uint32_t*)(T + b->tab_map) + b->map_off[p];
+        da.tile_job = (const uint32_t*)(T + b->tab_job);
+        da.batch = (const BatchPass*)(T + b->tab_pass) + (size_t)p * nl;
+        da.status = S[p % 2];
+        da.status_next = (p + 1 < b->maxD) ? S[(p + 1) % 2] : nullptr;
+        da.tile_counter = ctl + kCtlPassCnt + p;
+        da.err = ctl + kCtlErr;
+        double bytes = 0;
+        for (int i : b->large)
+            if (p < b->t[i].D) bytes += 2.0 * b->t[i].n * rec_bytes(b, b->t[i].r);
+        QSD_CK(timed(kDigitBatch, bytes, stream,
+                     [&] { return launch_digit_batch(da, b->rmax, b->crd_bytes, b->val_bytes, b->items, stream); }));
+    }
+#undef QSD_CK
+    return QSD_OK;
+}
+
+qsd_status qsd_batch_tune(qsd_batch_t b, const qsd_batch_io* io, void* ws, size_t ws_bytes, hipStream_t stream,
+                          int32_t reps, qsd_tuning* best, float* best_ms) {
+    if (!b || !ws) return QSD_ERR_NULL;
+    if (reps < 1) reps = 1;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return QSD_ERR_HIP;
+    qsd_tuning bt = b->tun;
+    float bms = -1.f;
+    qsd_status st = QSD_OK;
+    for (int items : {8, 16})
+        for (int rb : {6, 7, 8})
+            for (int cap : {0, 1024, kSmallCap}) {
+                const qsd_tuning cand{items, rb, cap};
+                if (qsd_batch_set_tuning(b, &cand) != QSD_OK || b->total > ws_bytes) continue;
+                if ((st = qsd_batch_bind(b, io, ws, ws_bytes, stream)) != QSD_OK) goto done;
+                if ((st = qsd_batch_transpose(b, ws, ws_bytes, stream)) != QSD_OK) goto done;  // warm-up
+                float mn = 1e30f;
+                for (int k = 0; k < reps; ++k) {
+                    hipEventRecord(e0, stream);
+                    if ((st = qsd_batch_transpose(b, ws, ws_bytes, stream)) != QSD_OK) goto done;
+                    hipEventRecord(e1, stream);
+                    if (hipEventSynchronize(e1) != hipSuccess) {
+                        st = QSD_ERR_HIP;
+                        goto done;
+                    }
+                    float ms = 0.f;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    mn = std::min(mn, ms);
+                }
+                if (bms < 0 || mn < bms) {
+                    bms = mn;
+                    bt = cand;
+                }
+            }
+    if (qsd_batch_set_tuning(b, &bt) == QSD_OK) st = qsd_batch_bind(b, io, ws, ws_bytes, stream);
+done:
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (best) *best = bt;
+    if (best_ms) *best_ms = bms;
+    return st;
+}
+
+qsd_status qsd_batch_graph(qsd_batch_t b, void* ws, size_t ws_bytes, qsd_graph_t* out) {
+    if (!b || !out) return QSD_ERR_NULL;
+    *out = nullptr;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return QSD_ERR_HIP;
+    hipGraph_t g = nullptr;
+    qsd_status st = QSD_OK;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        hipStreamDestroy(s);
+        return QSD_ERR_HIP;
+    }
+    st = qsd_batch_transpose(b, ws, ws_bytes, s);
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    hipStreamDestroy(s);
+    if (st != QSD_OK || ec != hipSuccess || !g) {
+        if (g) hipGraphDestroy(g);
+        return st != QSD_OK ? st : QSD_ERR_HIP;
+    }
+    auto* gr = new qsd_graph_s();
+    const hipError_t ei = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        delete gr;
+        return QSD_ERR_HIP;
+    }
+    *out = gr;
+    return QSD_OK;
+}
+
+qsd_status qsd_graph_launch(qsd_graph_t g, hipStream_t stream) {
+    if (!g || !g->exec) return QSD_ERR_NULL;
+    return hipGraphLaunch(g->exec, stream) == hipSuccess ? QSD_OK : QSD_ERR_HIP;
+}
+
+void qsd_graph_destroy(qsd_graph_t g) {
+    if (!g) return;
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    delete g;
 }
 
 }  // extern "C"

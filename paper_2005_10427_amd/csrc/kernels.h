@@ -44,6 +44,22 @@ inline int digit_items(int r, int crd_bytes, int val_bytes, int pref = 0) {
     return words <= 6 ? 16 : 8;
 }
 
+// One tensor's digit pass inside a batched launch (device table, one entry per tensor).
+struct BatchPass {
+    const void* src_crd[8];
+    const void* src_val;
+    void* dst_crd[8];
+    void* dst_val;
+    DevKey key;
+    int32_t lo, bits;
+    int32_t r;
+    uint32_t n;
+    const uint32_t* hist;       // 256 digit counts of this pass over the tensor
+    uint32_t tile0;             // first (stable) tile id of the tensor
+    int32_t active;             // 0: the tensor has no pass in this launch
+    uint32_t pad[2];
+};
+
 struct DigitArgs {
     const void* src_crd[8];
     const void* src_val;
@@ -61,8 +77,46 @@ struct DigitArgs {
     uint32_t* tile_counter;
     const uint64_t* large_ctl;  // segment mode
     const SegRec* large;        // segment mode
-    const uint32_t* tile_map;   // segment mode: large segment of every tile
+    const uint32_t* tile_map;   // segment mode: large segment of every tile;
+                                // batch mode: stable tile id of every launch-local tile
+    const uint32_t* tile_job;   // batch mode: tensor (table entry) of every stable tile
+    const BatchPass* batch;     // batch mode: this launch's table
     uint32_t* err;
+};
+
+// Upfront histograms of a batch: one job per (tensor, sub-key), a static tile range each.
+struct BatchHistJob {
+    const void* crd[8];
+    DevKey key[2];              // sub-keys, least significant first
+    int32_t r, nsub, npass;
+    int32_t lo[16];
+    int32_t bits[16];
+    int32_t sub[16];            // sub-key of every pass
+    uint32_t n;
+    uint32_t tile0;             // first stable tile of the tensor
+    uint32_t* hist;             // npass * 256 counts
+};
+
+struct BatchHistArgs {
+    const BatchHistJob* jobs;
+    const uint32_t* tile_job;   // stable tile -> job
+    uint32_t ntiles;
+    uint32_t tile;              // records per tile
+    uint32_t* status_zero;      // look-back words of the first launch, zeroed here
+};
+
+// A whole small tensor sorted in LDS by its flattened key (up to 2 sub-keys).
+struct BatchSmallJob {
+    const void* src_crd[8];
+    const void* src_val;
+    void* dst_crd[8];
+    void* dst_val;
+    DevKey key[2];
+    int32_t key_bits[2];
+    int32_t nsub;
+    int32_t r;
+    uint32_t n;
+    uint32_t pad;
 };
 
 struct HistArgs {
@@ -156,6 +210,11 @@ hipError_t launch_zero(const ZeroArgs& a, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_hist(const HistArgs& a, int r, int crd_bytes, int grid, hipStream_t s);
 hipError_t launch_digit(const DigitArgs& a, int r, int crd_bytes, int val_bytes, int items, hipStream_t s);
+hipError_t launch_digit_batch(const DigitArgs& a, int rmax, int crd_bytes, int val_bytes, int items,
+                              hipStream_t s);
+hipError_t launch_hist_batch(const BatchHistArgs& a, int rmax, int crd_bytes, int grid, hipStream_t s);
+hipError_t launch_small_batch(const BatchSmallJob* jobs, uint32_t njobs, int rmax, int crd_bytes,
+                              int val_bytes, hipStream_t s);
 hipError_t launch_boundary(const BoundArgs& a, int crd_bytes, hipStream_t s);
 hipError_t launch_classify(const ClassArgs& a, uint32_t max_segments, hipStream_t s);
 hipError_t launch_small(const SmallArgs& a, int crd_bytes, int val_bytes, uint32_t max_items,

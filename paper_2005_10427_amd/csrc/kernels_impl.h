@@ -1,0 +1,1292 @@
+// HIP kernels for gfx950 (CDNA4, wave64).
+//
+// The digit pass is a stable counting-sort pass (Alg. 1: count, prefix sum, move in input
+// order) made single-pass on the GPU:
+//   * the global count of every digit comes from an upfront histogram kernel (the count
+//     loop, done once for all digit passes of a key since counts do not depend on order);
+//   * each workgroup ranks a tile of records by digit with wave64 ballots (stable within the
+//     tile), publishes its per-digit counts and reads its predecessors' counts with a
+//     decoupled look-back (Merrill & Garland, 2016) -- the "private count arrays merged in
+//     order" of Sec. 3.1, merged in (digit-major, tile-minor) order;
+//   * the tile is reordered through LDS so that every digit's run is written contiguously,
+//     and whole records (all coordinates and the value bits) move, so no final gather runs.
+// Bucketed groups (Alg. 2) are sorted segment by segment (the paper's decomposition along
+// bucket boundaries, Sec. 3.2): short segments entirely in LDS, long ones by the same digit
+// pass restricted to each segment.
+#pragma once
+#include "kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+namespace qsd {
+namespace {
+
+constexpr uint32_t kFlagA = 1u << 30;  // aggregate of this tile only
+constexpr uint32_t kFlagP = 2u << 30;  // inclusive prefix up to this tile
+constexpr uint32_t kCntMask = (1u << 30) - 1;
+constexpr uint32_t kSpinLimit = 1u << 20;
+constexpr int kWaves = kBlock / 64;
+
+__device__ __forceinline__ uint32_t ld_status(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_status(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+// Wait until this wave's LDS operations have completed (lgkmcnt(0); vmcnt and expcnt left at
+// their maximum).  The barrier of __syncthreads() does not wait for LDS atomics that return
+// nothing on this target, so a flush of LDS-atomic counters must wait explicitly first.
+__device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+__device__ __forceinline__ void sync_after_lds_atomics() {
+    lds_wait();
+    __syncthreads();
+}
+// number of set bits of m in lanes below this one
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread over the block; s_tmp holds kWaves words.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t inc = wave_incl_scan(v, lane);
+    if (lane == 63) s_tmp[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const uint32_t s = s_tmp[w];
+        before += (w < wave) ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    if (total) *total = tot;
+    return before + inc - v;
+}
+
+template <typename CT>
+__device__ __forceinline__ uint64_t compose_key(const CT (&c)[8], const DevKey& k, int r) {
+    uint64_t key = 0;
+    for (int m = 0; m < r; ++m)
+        if (k.mask[m]) key |= (((uint64_t)c[m] >> k.src_lo[m]) & k.mask[m]) << k.dst[m];
+    return key;
+}
+
+// ------------------------------------------------------------------------------ utility
+
+__global__ void __launch_bounds__(256) k_zero(ZeroArgs a) {
+    for (int r = 0; r < 4; ++r) {
+        uint32_t* p = a.ptr[r];
+        if (!p) continue;
+        for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < a.words[r]; i += gridDim.x * 256ull)
+            p[i] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                              uint64_t n16, const uint8_t* __restrict__ sb,
+                                              uint8_t* __restrict__ db, uint64_t bytes) {
+    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n16; i += gridDim.x * 256ull) dst[i] = src[i];
+    for (uint64_t i = n16 * 16 + blockIdx.x * 256ull + threadIdx.x; i < bytes; i += gridDim.x * 256ull)
+        db[i] = sb[i];
+}
+
+// ------------------------------------------------------------------------------ histograms
+
+// Counts of every digit of every pass of one key, over all records (global) or per large
+// segment.  Also clears the look-back words of the key's first digit pass.
+template <int R, typename CT>
+__global__ void __launch_bounds__(256) k_hist(HistArgs a) {
+    constexpr int U = 8;  // records per thread per round (independent loads in flight)
+    constexpr int MAXP = 16;
+    __shared__ uint32_t s_h[MAXP * kBins + kBins];  // + one spare block for out-of-range items
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int npass = a.npass;
+    const int words = npass * kBins;
+    for (int i = tid; i < words; i += kBlock) s_h[i] = 0;
+    // per-pass shift and mask, uniform: kept in scalar registers for the whole kernel
+    uint32_t plo[MAXP], pmask[MAXP];
+#pragma unroll
+    for (int p = 0; p < MAXP; ++p) {
+        plo[p] = p < npass ? (uint32_t)a.lo[p] : 0u;
+        pmask[p] = p < npass ? (1u << a.bits[p]) - 1u : 0u;
+    }
+    const uint32_t spare = MAXP * kBins;  // items past the end count into the spare block
+
+    // count the digits of records [lo, hi) with U loads per key mode in flight
+    auto count_range = [&](uint32_t lo, uint32_t hi) {
+        for (uint32_t base = lo; base < hi; base += kBlock * U) {
+            uint64_t key[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) key[u] = 0;
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                if (!a.key.mask[m]) continue;
+                const CT* src = (const CT*)a.crd[m];
+                CT c[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t e = base + u * kBlock + tid;
+                    c[u] = e < hi ? src[e] : CT(0);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    key[u] |= (((uint64_t)c[u] >> a.key.src_lo[m]) & a.key.mask[m]) << a.key.dst[m];
+            }
+#pragma unroll
+            for (int p = 0; p < MAXP; ++p) {
+                if (p >= npass) break;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t e = base + u * kBlock + tid;
+                    const uint32_t slot = e < hi ? p * kBins + ((uint32_t)(key[u] >> plo[p]) & pmask[p]) : spare;
+                    // sorted inputs put long runs of one digit in consecutive lanes: add each
+                    // run once, from its first lane, instead of one conflicting atomic per lane
+                    const uint32_t prev = __shfl_up(slot, 1, 64);
+                    const bool head = (lane == 0) || (prev != slot);
+                    const uint64_t heads = ballot(head);
+                    if (head) {
+                        const uint64_t after = (lane == 63) ? 0ull : (heads >> (lane + 1));
+                        const uint32_t run = after ? (uint32_t)__builtin_ctzll(after) + 1u : 64u - lane;
+                        atomicAdd(&s_h[slot], run);
+                    }
+                }
+            }
+        }
+    };
+    __syncthreads();
+    if (!a.seg_mode) {
+        const uint32_t chunk = kBlock * U;
+        const uint32_t nchunks = (a.n + chunk - 1) / chunk;
+        const uint32_t per = (nchunks + gridDim.x - 1) / gridDim.x;
+        const uint32_t c0 = blockIdx.x * per, c1 = min(nchunks, c0 + per);
+        if (c0 < c1) count_range(c0 * chunk, min(a.n, c1 * chunk));
+        sync_after_lds_atomics();
+        for (int i = tid; i < words; i += kBlock) {
+            const uint32_t c = s_h[i];
+            if (c) atomicAdd(&a.hist[i], c);
+        }
+        for (uint64_t i = blockIdx.x * (uint64_t)kBlock + tid; i < a.status_words; i += gridDim.x * (uint64_t)kBlock)
+            a.status_zero[i] = 0;
+        return;
+    }
+    // segment mode: a static range of large-segment tiles per workgroup; histograms are
+    // flushed to the segment's block whenever the segment changes
+    const uint32_t nT = (uint32_t)*a.large_ctl;
+    const uint32_t per = (nT + gridDim.x - 1) / gridDim.x;
+    const uint32_t t0 = blockIdx.x * per, t1 = min(nT, t0 + per);
+    uint32_t cur = 0xFFFFFFFFu;
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t k = a.tile_map[t];
+        if (k != cur) {
+            sync_after_lds_atomics();
+            if (cur != 0xFFFFFFFFu) {
+                for (int i = tid; i < words; i += kBlock) {
+                    const uint32_t c = s_h[i];
+                    if (c) atomicAdd(&a.hist[(size_t)cur * a.hist_stride + i], c);
+                    s_h[i] = 0;
+                }
+            }
+            cur = k;
+            __syncthreads();
+        }
+        const SegRec s = a.large[k];
+        const uint32_t start = s.start + (t - s.tile_base) * a.tile;
+        const uint32_t end = min(s.start + s.len, start + a.tile);
+        count_range(start, end);
+        a.status_zero[(size_t)t * kBins + tid] = 0;
+    }
+    sync_after_lds_atomics();
+    if (cur != 0xFFFFFFFFu) {
+        for (int i = tid; i < words; i += kBlock) {
+            const uint32_t c = s_h[i];
+            if (c) atomicAdd(&a.hist[(size_t)cur * a.hist_stride + i], c);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------ digit pass
+
+constexpr int kLookWin = 8;
+
+// Decoupled look-back done by one whole wave for one counter: lane l reads the status of
+// tile j - l, so 64 predecessors are inspected per round trip.  Statuses are at
+// status[tile * stride + slot]; `lowest` is the first tile (it always publishes a prefix).
+// Every lane returns the same exclusive prefix.
+__device__ __forceinline__ uint32_t wave_look_back(const uint32_t* status, uint32_t t, uint32_t stride,
+                                                   uint32_t slot, uint32_t lowest, uint32_t* err) {
+    const int lane = threadIdx.x & 63;
+    uint32_t excl = 0, spins = 0;
+    uint32_t j = t - 1;  // most recent predecessor not yet accounted for
+    for (;;) {
+        const uint32_t avail = j - lowest + 1;
+        const uint32_t w = (uint32_t)lane < avail ? ld_status(&status[(size_t)(j - lane) * stride + slot]) : 0u;
+        const uint32_t f = w & ~kCntMask;
+        const uint64_t notready = ballot((uint32_t)lane < avail && f == 0);
+        const uint64_t prefix = ballot(f == kFlagP);
+        const uint32_t stop_nr = notready ? (uint32_t)__builtin_ctzll(notready) : 64u;
+        const uint32_t stop_p = prefix ? (uint32_t)__builtin_ctzll(prefix) : 64u;
+        // lanes before the first not-ready one are usable; include the first prefix if it
+        // comes before that
+        const uint32_t use = stop_p < stop_nr ? stop_p + 1 : min(stop_nr, min(avail, 64u));
+        uint32_t part = (uint32_t)lane < use ? (w & kCntMask) : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        excl += part;
+        if (stop_p < stop_nr) return excl;
+        j -= use;
+        if (stop_nr < 64 && stop_nr < avail) {
+            if (++spins > kSpinLimit) {
+                if (lane == 0) atomicOr(err, 1u);
+                return excl;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+}
+
+// Decoupled look-back for one digit: sum the counts of the predecessors of tile t back to
+// the nearest one that has published an inclusive prefix.  kLookWin status words are read
+// per round trip; `lowest` (the first tile of the segment) always publishes a prefix.
+__device__ __forceinline__ uint32_t look_back(const uint32_t* status, uint32_t t, uint32_t lowest,
+                                              uint32_t b, uint32_t* err) {
+    uint32_t excl = 0, spins = 0;
+    uint32_t j = t - 1;  // next predecessor to read
+    {
+        // usually the immediate predecessor has already published its prefix
+        const uint32_t w = ld_status(&status[(size_t)j * kBins + b]);
+        const uint32_t f = w & ~kCntMask;
+        if (f == kFlagP) return w & kCntMask;
+        if (f == kFlagA) {
+            excl = w & kCntMask;
+            --j;
+        }
+    }
+    for (;;) {
+        const uint32_t avail = j - lowest + 1;
+        uint32_t w[kLookWin];
+#pragma unroll
+        for (int i = 0; i < kLookWin; ++i)
+            w[i] = ((uint32_t)i < avail) ? ld_status(&status[(size_t)(j - i) * kBins + b]) : 0u;
+        uint32_t used = 0;
+        bool done = false, stalled = false;
+#pragma unroll
+        for (int i = 0; i < kLookWin; ++i) {
+            if (done || stalled || (uint32_t)i >= avail) continue;
+            const uint32_t f = w[i] & ~kCntMask;
+            if (f == 0) {
+                stalled = true;
+                continue;
+            }
+            excl += w[i] & kCntMask;
+            ++used;
+            if (f == kFlagP) done = true;
+        }
+        if (done) return excl;
+        j -= used;
+        if (stalled) {
+            if (++spins > kSpinLimit) {
+                atomicOr(err, 1u);
+                return excl;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+}
+
+// Move one array of the tile: registers -> LDS (local slot lp) -> global (slot gp), with
+// the next array's loads issued before the barrier.
+template <typename T, int ITEMS>
+__device__ __forceinline__ void load_items(const T* __restrict__ src, uint32_t start, uint32_t len,
+                                           uint32_t wb, T (&x)[ITEMS]) {
+    const T* tile = src + start;  // uniform base; per-item offsets stay small
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t off = wb + i * 64;
+        x[i] = off < len ? tile[off] : T(0);
+    }
+}
+
+template <typename T, int ITEMS>
+__device__ __forceinline__ void stage_items(T* sx, uint32_t len, uint32_t wb, const T (&x)[ITEMS],
+                                            const uint32_t (&lp)[ITEMS]) {
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        if (wb + i * 64 < len) sx[lp[i]] = x[i];
+}
+
+template <typename T, int ITEMS>
+__device__ __forceinline__ void drain_items(const T* sx, T* __restrict__ dst, uint32_t len,
+                                            const uint32_t (&gp)[ITEMS]) {
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = i * kBlock + threadIdx.x;
+        if (j < len) dst[gp[i]] = sx[j];
+    }
+}
+
+// MODE 0: one segment [0, n).  MODE 1: the large segments of a bucketed group.  MODE 2: a
+// batch of tensors (each tensor is one segment; its parameters come from a device table).
+template <int R, typename CT, typename VT, int ITEMS, int MODE>
+__global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
+    constexpr int TILE = kBlock * ITEMS;
+    __shared__ uint64_t s_x[TILE];               // record exchange (4- or 8-byte words)
+    __shared__ uint32_t s_cnt[kWaves * kBins];   // per-wave digit counters, then wave prefixes
+    __shared__ uint32_t s_tstart[kBins];         // first local slot of each digit
+    __shared__ uint32_t s_base[kBins];           // global slot of local slot 0 of each digit
+    __shared__ uint8_t s_dig[TILE];
+    __shared__ uint32_t s_tmp[2 * kWaves];
+    __shared__ uint32_t s_geo[6];                // tile, start, len, segment base, k, first tile
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    for (;;) {
+        if (tid == 0) {
+            const uint32_t lt = atomicAdd(a.tile_counter, 1u);
+            uint32_t t = lt, ntiles = a.ntiles, start = 0, len = 0, base = 0, k = 0, lowest = 0;
+            bool live = false;
+            if (MODE == 1) {
+                ntiles = (uint32_t)*a.large_ctl;
+                if (lt < ntiles) {
+                    k = a.tile_map[lt];
+                    const SegRec s = a.large[k];
+                    base = s.start;
+                    lowest = s.tile_base;
+                    start = s.start + (lt - s.tile_base) * TILE;
+                    len = min((uint32_t)TILE, s.start + s.len - start);
+                    live = true;
+                }
+            } else if (MODE == 2) {
+                if (lt < ntiles) {
+                    t = a.tile_map[lt];  // stable tile id: the look-back words are indexed by it
+                    k = a.tile_job[t];
+                    const uint32_t t0 = a.batch[k].tile0;
+                    lowest = t0;
+                    start = (t - t0) * TILE;
+                    len = min((uint32_t)TILE, a.batch[k].n - start);
+                    live = true;
+                }
+            } else if (lt < ntiles) {
+                start = lt * TILE;
+                len = min((uint32_t)TILE, a.n - start);
+                live = true;
+            }
+            s_geo[0] = live ? t : 0xFFFFFFFFu;
+            s_geo[1] = start;
+            s_geo[2] = len;
+            s_geo[3] = base;
+            s_geo[4] = k;
+            s_geo[5] = lowest;
+        }
+        __syncthreads();
+        // tile geometry is uniform: keep it in scalar registers
+        const uint32_t t = __builtin_amdgcn_readfirstlane(s_geo[0]);
+        if (t == 0xFFFFFFFFu) break;
+        const uint32_t start = __builtin_amdgcn_readfirstlane(s_geo[1]);
+        const uint32_t len = __builtin_amdgcn_readfirstlane(s_geo[2]);
+        const uint32_t seg_base = __builtin_amdgcn_readfirstlane(s_geo[3]);
+        const uint32_t k = __builtin_amdgcn_readfirstlane(s_geo[4]);
+        const uint32_t lowest = __builtin_amdgcn_readfirstlane(s_geo[5]);
+        const bool first = (t == lowest);
+        const BatchPass* J = a.batch + k;  // batch mode only
+        const DevKey& key = MODE == 2 ? J->key : a.key;
+        const int lo_bit = MODE == 2 ? J->lo : a.lo;
+        const int nbits = MODE == 2 ? J->bits : a.bits;
+        const int r = MODE == 2 ? J->r : R;
+        const void* const* src_crd = MODE == 2 ? J->src_crd : a.src_crd;
+        void* const* dst_crd = MODE == 2 ? J->dst_crd : a.dst_crd;
+        const void* src_val = MODE == 2 ? J->src_val : a.src_val;
+        void* dst_val = MODE == 2 ? J->dst_val : a.dst_val;
+        const uint32_t* hist = MODE == 2 ? J->hist : a.hist + (size_t)k * a.hist_stride;
+        const uint32_t dmask = (1u << nbits) - 1u;
+        const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;  // wave w owns a contiguous slice
+
+        // ---- key modes first: the tile's digit counts are published as early as possible;
+        // the other arrays are loaded while the look-back waits on the predecessors
+        CT c[R][ITEMS];
+        VT v[ITEMS];
+        uint32_t dg[ITEMS], lp[ITEMS];
+#pragma unroll
+        for (int m = 0; m < R; ++m)
+            if (m < r && key.mask[m]) load_items<CT, ITEMS>((const CT*)src_crd[m], start, len, wb, c[m]);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            uint64_t kv = 0;
+#pragma unroll
+            for (int m = 0; m < R; ++m)
+                if (m < r && key.mask[m]) kv |= (((uint64_t)c[m][i] >> key.src_lo[m]) & key.mask[m]) << key.dst[m];
+            dg[i] = (uint32_t)(kv >> lo_bit) & dmask;
+        }
+
+        // ---- stable rank inside each wave: ballot-match the digit, count lanes below
+        for (int b = lane; b < kBins; b += 64) s_cnt[wave * kBins + b] = 0;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const bool ok = (wb + i * 64) < len;
+            const uint32_t d = dg[i];
+            uint64_t peers = ballot(ok);
+            for (int b = 0; b < nbits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = ballot(bit);
+                peers &= bit ? bb : ~bb;
+            }
+            const uint32_t below = lanes_below(peers);
+            uint32_t old = 0;
+            if (ok) old = s_cnt[wave * kBins + d];
+            lp[i] = old + below;
+            if (ok && below == 0) s_cnt[wave * kBins + d] = old + (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+
+        // ---- per digit: wave prefixes, tile count, look-back for the global offset
+        {
+            const uint32_t b = tid;
+            uint32_t run = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t x = s_cnt[w * kBins + b];
+                s_cnt[w * kBins + b] = run;
+                run += x;
+            }
+            const uint32_t tcnt = run;
+            uint32_t* st = a.status + (size_t)t * kBins;
+            st_status(&st[b], (first ? kFlagP : kFlagA) | tcnt);
+            // the rest of the records, in flight during the scans and the look-back
+#pragma unroll
+            for (int m = 0; m < R; ++m)
+                if (m < r && !key.mask[m]) load_items<CT, ITEMS>((const CT*)src_crd[m], start, len, wb, c[m]);
+            load_items<VT, ITEMS>((const VT*)src_val, start, len, wb, v);
+            const uint32_t tstart = block_excl_scan(tcnt, s_tmp, nullptr);
+            const uint32_t hstart = block_excl_scan(hist[b], s_tmp + kWaves, nullptr);
+            uint32_t excl = 0;
+            if (!first) {
+                excl = look_back(a.status, t, lowest, b, a.err);
+                st_status(&st[b], kFlagP | (excl + tcnt));
+            }
+            s_tstart[b] = tstart;
+            s_base[b] = seg_base + hstart + excl - tstart;
+            if (a.status_next) a.status_next[(size_t)t * kBins + b] = 0;
+        }
+        __syncthreads();
+
+        // ---- local slot of every record, then the digit of every local slot
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if ((wb + i * 64) < len) {
+                const uint32_t d = dg[i];
+                lp[i] += s_tstart[d] + s_cnt[wave * kBins + d];
+                s_dig[lp[i]] = (uint8_t)d;
+            }
+        }
+        __syncthreads();
+        uint32_t gp[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = i * kBlock + tid;
+            gp[i] = (j < len) ? s_base[s_dig[j]] + j : 0;
+        }
+
+        // ---- move every array through LDS: contiguous runs per digit on the way out
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            if (m >= r) break;
+            stage_items<CT, ITEMS>((CT*)s_x, len, wb, c[m], lp);
+            __syncthreads();
+            drain_items<CT, ITEMS>((const CT*)s_x, (CT*)dst_crd[m], len, gp);
+            __syncthreads();
+        }
+        stage_items<VT, ITEMS>((VT*)s_x, len, wb, v, lp);
+        __syncthreads();
+        drain_items<VT, ITEMS>((const VT*)s_x, (VT*)dst_val, len, gp);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------ buckets
+
+// Segment starts: positions where the prefix (sigma_1..sigma_l) differs from the previous
+// record (Alg. 2's bucket discovery), compacted in order with a single-word look-back.
+template <typename CT>
+__global__ void __launch_bounds__(256) k_boundary(BoundArgs a) {
+    constexpr int ITEMS = kBoundTile / kBlock;
+    __shared__ uint32_t s_wsum[kWaves];
+    __shared__ uint32_t s_geo[2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) {
+        const uint32_t t = atomicAdd(a.tile_counter, 1u);
+        s_geo[0] = t;
+    }
+    __syncthreads();
+    const uint32_t t = s_geo[0];
+    const uint32_t start = t * kBoundTile;
+    if (start >= a.n) return;
+    const uint32_t len = min((uint32_t)kBoundTile, a.n - start);
+    const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
+    uint64_t flags[ITEMS];
+    bool f[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) f[i] = (start + wb + i * 64 == 0);
+    for (int j = 0; j < a.nprefix; ++j) {  // all loads of one prefix mode in flight together
+        const CT* p = (const CT*)a.crd[a.prefix[j]];
+        CT cur[ITEMS], prv[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t off = wb + i * 64;
+            const uint32_t e = start + off;
+            const bool ok = off < len && e > 0;
+            cur[i] = ok ? p[e] : CT(0);
+            prv[i] = ok ? p[e - 1] : CT(0);
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) f[i] |= cur[i] != prv[i];
+    }
+    uint32_t wcount = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        flags[i] = ballot(f[i] && (wb + i * 64 < len));
+        wcount += (uint32_t)__popcll(flags[i]);
+    }
+    if (lane == 0) s_wsum[wave] = wcount;
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += s_wsum[w];
+        uint32_t* st = a.status + t;
+        if (lane == 0) st_status(st, (t == 0 ? kFlagP : kFlagA) | tot);
+        const uint32_t excl = t == 0 ? 0u : wave_look_back(a.status, t, 1, 0, 0, a.err);
+        if (lane == 0) {
+            if (t != 0) st_status(st, kFlagP | (excl + tot));
+            s_geo[1] = excl;
+            if (start + len == a.n) {
+                *a.nb_out = excl + tot;
+                a.seg_start[excl + tot] = a.n;
+                a.region_seg[(a.n + kRegion - 1) / kRegion] = excl + tot;
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t pos = s_geo[1];
+    for (int w = 0; w < wave; ++w) pos += s_wsum[w];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint64_t f = flags[i];
+        const uint32_t e = start + wb + i * 64;
+        const uint32_t before = pos + lanes_below(f);  // segments starting before e
+        if ((f >> lane) & 1ull) a.seg_start[before] = e;
+        if (wb + i * 64 < len && e % (uint32_t)kRegion == 0) a.region_seg[e / kRegion] = before;
+        pos += (uint32_t)__popcll(f);
+    }
+}
+
+// Sort segments into three classes: tiny (left to the region pass), medium (one workgroup
+// each) and large (digit passes over tiles of the segment).
+__global__ void __launch_bounds__(256) k_classify(ClassArgs a) {
+    const uint32_t nb = *a.nb;
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nb; k += gridDim.x * kBlock) {
+        const uint32_t s = a.seg_start[k];
+        const uint32_t len = a.seg_start[k + 1] - s;
+        if (len <= (uint32_t)kTinyLen) continue;
+        if (len <= (uint32_t)kSmallCap) {
+            const uint32_t i = atomicAdd(a.nmed, 1u);
+            a.med[i] = make_uint2(s, len);
+        } else {
+            const uint32_t tiles = (len + a.tile - 1) / a.tile;
+            const unsigned long long old =
+                atomicAdd((unsigned long long*)a.large_ctl, (1ull << 32) | (unsigned long long)tiles);
+            const uint32_t idx = (uint32_t)(old >> 32);
+            SegRec rec;
+            rec.start = s;
+            rec.len = len;
+            rec.tile_base = (uint32_t)old;
+            rec.pad = 0;
+            a.large[idx] = rec;
+            for (uint32_t i = 0; i < tiles; ++i) a.tile_map[rec.tile_base + i] = idx;
+            uint32_t* h = a.seg_hist + (size_t)idx * a.hist_stride;
+            for (uint32_t i = 0; i < a.hist_stride; ++i) h[i] = 0;
+        }
+    }
+}
+
+// Stable sort of short runs of records entirely in LDS, by (segment number, group key).
+// Work items: the tiny segments starting in each region of kRegion records (their union
+// is one run of fewer than kSmallCap records), then every medium segment.  A run's records
+// are loaded into registers right away (all loads in flight at once), sorted through LDS
+// by LSD passes over the key bits that vary inside the run, and written back in place.
+template <int R, typename CT, typename VT>
+__global__ void __launch_bounds__(256) k_small(SmallArgs a) {
+    constexpr int CAP = kSmallCap, ITEMS = CAP / kBlock;
+    __shared__ uint64_t s_key[CAP];   // keys, then staging of each array
+    __shared__ uint16_t s_ia[CAP], s_ib[CAP], s_seg[CAP];
+    __shared__ uint32_t s_cnt[kWaves * kBins];
+    __shared__ uint32_t s_bstart[kBins];
+    __shared__ uint32_t s_tmp[2 * kWaves];
+    __shared__ uint64_t s_red[2 * kWaves];
+    __shared__ uint32_t s_run[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    for (uint32_t item = blockIdx.x;; item += gridDim.x) {
+        const uint32_t nmed = *a.nmed;
+        if (item >= a.nregions + nmed) break;
+        if (tid == 0) {
+            uint32_t rs = 0, re = 0, sa = 0, se = 0;
+            if (item < a.nregions) {
+                // segments starting in [item*kRegion, (item+1)*kRegion): sa .. se-1
+                sa = a.region_seg[item];
+                se = a.region_seg[item + 1];
+                // only the last segment starting here can be longer than the region
+                if (se > sa && a.seg_start[se] - a.seg_start[se - 1] > (uint32_t)kTinyLen) --se;
+                rs = a.seg_start[sa];
+                re = a.seg_start[se];
+            } else {
+                const uint2 md = a.med[item - a.nregions];
+                rs = md.x;
+                re = md.x + md.y;
+            }
+            s_run[0] = rs;
+            s_run[1] = re;
+            s_run[2] = sa;
+            s_run[3] = se;
+        }
+        __syncthreads();
+        const uint32_t rs = __builtin_amdgcn_readfirstlane(s_run[0]);
+        const uint32_t L = __builtin_amdgcn_readfirstlane(s_run[1]) - rs;
+        const uint32_t sa = __builtin_amdgcn_readfirstlane(s_run[2]);
+        const uint32_t se = __builtin_amdgcn_readfirstlane(s_run[3]);
+        if (L == 0) {
+            __syncthreads();
+            continue;
+        }
+        const bool region = item < a.nregions;
+
+        // ---- the whole run into registers: slot j = i*kBlock + tid
+        CT c[R][ITEMS];
+        VT v[ITEMS];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const CT* src = (const CT*)a.src_crd[m] + rs;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t j = i * kBlock + tid;
+                c[m][i] = j < L ? src[j] : CT(0);
+            }
+        }
+        {
+            const VT* src = (const VT*)a.src_val + rs;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t j = i * kBlock + tid;
+                v[i] = j < L ? src[j] : VT(0);
+            }
+        }
+
+        // ---- segment number of every record of the run
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) s_seg[i * kBlock + tid] = 0;
+        __syncthreads();
+        if (region) {
+            uint32_t st[ITEMS / 2];
+#pragma unroll
+            for (int i = 0; i < ITEMS / 2; ++i) {  // at most kRegion segments start in a region
+                const uint32_t s2 = sa + 1 + i * kBlock + tid;
+                st[i] = s2 < se ? a.seg_start[s2] : 0xFFFFFFFFu;
+            }
+#pragma unroll
+            for (int i = 0; i < ITEMS / 2; ++i)
+                if (st[i] != 0xFFFFFFFFu) s_seg[st[i] - rs] = 1;
+        }
+        __syncthreads();
+        {
+            // blocked inclusive scan: thread tid owns slots [tid*ITEMS, tid*ITEMS+ITEMS)
+            uint32_t loc[ITEMS], sum = 0;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t j = tid * ITEMS + i;
+                sum += (j < L) ? s_seg[j] : 0;
+                loc[i] = sum;
+            }
+            const uint32_t before = block_excl_scan(sum, s_tmp, nullptr);
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t j = tid * ITEMS + i;
+                if (j < L) s_seg[j] = (uint16_t)(before + loc[i]);
+            }
+        }
+        __syncthreads();
+        // ---- composite keys: (segment number << key bits) | group key
+        uint64_t kor = 0, kand = ~0ull;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = i * kBlock + tid;
+            if (j < L) {
+                uint64_t key = 0;
+#pragma unroll
+                for (int m = 0; m < R; ++m)
+                    if (a.key.mask[m]) key |= (((uint64_t)c[m][i] >> a.key.src_lo[m]) & a.key.mask[m]) << a.key.dst[m];
+                key |= (uint64_t)s_seg[j] << a.key_bits;
+                s_key[j] = key;
+                kor |= key;
+                kand &= key;
+            }
+            s_ia[j] = (uint16_t)j;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            kor |= __shfl_xor(kor, o, 64);
+            kand &= __shfl_xor(kand, o, 64);
+        }
+        if (lane == 0) {
+            s_red[wave] = kor;
+            s_red[kWaves + wave] = kand;
+        }
+        __syncthreads();
+        kor = 0;
+        kand = ~0ull;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            kor |= s_red[w];
+            kand &= s_red[kWaves + w];
+        }
+        const uint64_t vary = kor ^ kand;
+        // ---- LSD passes over the bits that vary inside this run
+        uint16_t* cur = s_ia;
+        uint16_t* nxt = s_ib;
+        if (vary) {
+            const int lo = __builtin_ctzll(vary), hi = 63 - __builtin_clzll(vary);
+            for (int sh = lo; sh <= hi; sh += 8) {
+                const int nbits = min(8, hi - sh + 1);
+                const uint32_t dmask = (1u << nbits) - 1u;
+                if (((vary >> sh) & dmask) == 0) continue;  // digit constant over the run
+                for (int b = lane; b < kBins; b += 64) s_cnt[wave * kBins + b] = 0;
+                uint32_t dg[ITEMS], lp[ITEMS];
+                uint16_t sv[ITEMS];
+                const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t j = wb + i * 64;
+                    const bool ok = j < L;
+                    sv[i] = ok ? cur[j] : 0;
+                    dg[i] = ok ? (uint32_t)(s_key[sv[i]] >> sh) & dmask : 0;
+                }
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const bool ok = (wb + i * 64) < L;
+                    const uint32_t d = dg[i];
+                    uint64_t peers = ballot(ok);
+                    for (int b = 0; b < nbits; ++b) {
+                        const bool bit = (d >> b) & 1u;
+                        const uint64_t bb = ballot(bit);
+                        peers &= bit ? bb : ~bb;
+                    }
+                    const uint32_t below = lanes_below(peers);
+                    uint32_t old = 0;
+                    if (ok) old = s_cnt[wave * kBins + d];
+                    lp[i] = old + below;
+                    if (ok && below == 0) s_cnt[wave * kBins + d] = old + (uint32_t)__popcll(peers);
+                }
+                __syncthreads();
+                {
+                    const uint32_t b = tid;
+                    uint32_t run = 0;
+#pragma unroll
+                    for (int w = 0; w < kWaves; ++w) {
+                        const uint32_t x = s_cnt[w * kBins + b];
+                        s_cnt[w * kBins + b] = run;
+                        run += x;
+                    }
+                    s_bstart[b] = block_excl_scan(run, s_tmp, nullptr);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    if ((wb + i * 64) < L) {
+                        const uint32_t d = dg[i];
+                        nxt[lp[i] + s_bstart[d] + s_cnt[wave * kBins + d]] = sv[i];
+                    }
+                }
+                __syncthreads();
+                uint16_t* t = cur;
+                cur = nxt;
+                nxt = t;
+            }
+        }
+        // ---- write every array back in sorted order: stage by original slot, gather by perm
+        uint16_t pm[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) pm[i] = cur[i * kBlock + tid];
+#pragma unroll
+        for (int m = 0; m <= R; ++m) {
+            __syncthreads();
+            if (m < R) {
+                CT* st = (CT*)s_key;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) st[i * kBlock + tid] = c[m][i];
+                __syncthreads();
+                CT* dst = (CT*)a.dst_crd[m] + rs;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t j = i * kBlock + tid;
+                    if (j < L) dst[j] = st[pm[i]];
+                }
+            } else {
+                VT* st = (VT*)s_key;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) st[i * kBlock + tid] = v[i];
+                __syncthreads();
+                VT* dst = (VT*)a.dst_val + rs;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t j = i * kBlock + tid;
+                    if (j < L) dst[j] = st[pm[i]];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------ batches
+
+// Upfront digit histograms of every pass of every tensor of a batch.  Each workgroup takes a
+// static range of stable tiles and flushes its counts whenever the tensor changes.  Also
+// clears the look-back words of the first batched launch.
+template <int R, typename CT>
+__global__ void __launch_bounds__(256) k_hist_batch(BatchHistArgs a) {
+    __shared__ uint32_t s_h[16 * kBins];
+    __shared__ uint32_t s_pp[16];  // lo | bits << 8 | sub << 16
+    const int tid = threadIdx.x, lane = tid & 63;
+    const uint32_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;
+    const uint32_t t0 = blockIdx.x * per, t1 = min(a.ntiles, t0 + per);
+    uint32_t cur = 0xFFFFFFFFu;
+    int words = 0;
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t j = a.tile_job[t];
+        if (j != cur) {
+            sync_after_lds_atomics();
+            if (cur != 0xFFFFFFFFu) {
+                uint32_t* h = a.jobs[cur].hist;
+                for (int i = tid; i < words; i += kBlock) {
+                    const uint32_t c = s_h[i];
+                    if (c) atomicAdd(&h[i], c);
+                }
+            }
+            cur = j;
+            words = a.jobs[j].npass * kBins;
+            for (int i = tid; i < words; i += kBlock) s_h[i] = 0;
+            if (tid < a.jobs[j].npass)
+                s_pp[tid] = (uint32_t)a.jobs[j].lo[tid] | ((uint32_t)a.jobs[j].bits[tid] << 8) |
+                            ((uint32_t)a.jobs[j].sub[tid] << 16);
+            __syncthreads();
+        }
+        const BatchHistJob& J = a.jobs[j];
+        const int r = J.r, nsub = J.nsub, npass = J.npass;
+        const uint32_t start = (t - J.tile0) * a.tile;
+        const uint32_t end = min(J.n, start + a.tile);
+        for (uint32_t base = start; base < end; base += kBlock) {
+            const uint32_t e = base + tid;
+            const bool ok = e < end;
+            CT c[R];
+#pragma unroll
+            for (int m = 0; m < R; ++m) c[m] = (m < r && ok) ? ((const CT*)J.crd[m])[e] : CT(0);
+            uint64_t kv[2] = {0, 0};
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                if (q >= nsub) break;
+#pragma unroll
+                for (int m = 0; m < R; ++m)
+                    if (m < r && J.key[q].mask[m])
+                        kv[q] |= (((uint64_t)c[m] >> J.key[q].src_lo[m]) & J.key[q].mask[m]) << J.key[q].dst[m];
+            }
+            for (int p = 0; p < npass; ++p) {
+                const uint32_t pp = __builtin_amdgcn_readfirstlane(s_pp[p]);
+                const uint64_t k = (pp >> 16) ? kv[1] : kv[0];
+                const uint32_t slot = ok ? p * kBins + ((uint32_t)(k >> (pp & 0xFF)) & ((1u << ((pp >> 8) & 0xFF)) - 1u))
+                                         : 0xFFFFFFFFu;
+                const uint32_t prev = __shfl_up(slot, 1, 64);
+                const bool head = ok && ((lane == 0) || (prev != slot));
+                const uint64_t heads = ballot(head || !ok);
+                if (head) {
+                    const uint64_t after = (lane == 63) ? 0ull : (heads >> (lane + 1));
+                    const uint32_t run = after ? (uint32_t)__builtin_ctzll(after) + 1u : 64u - lane;
+                    atomicAdd(&s_h[slot], run);
+                }
+            }
+        }
+        a.status_zero[(size_t)t * kBins + tid] = 0;
+    }
+    sync_after_lds_atomics();
+    if (cur != 0xFFFFFFFFu) {
+        uint32_t* h = a.jobs[cur].hist;
+        for (int i = tid; i < words; i += kBlock) {
+            const uint32_t c = s_h[i];
+            if (c) atomicAdd(&h[i], c);
+        }
+    }
+}
+
+// One small tensor per workgroup, sorted entirely in LDS by its flattened key: LSD passes
+// over the varying bits of every sub-key (least significant sub-key first), then every
+// array written out in sorted order.
+template <int R, typename CT, typename VT>
+__global__ void __launch_bounds__(256) k_small_batch(const BatchSmallJob* __restrict__ jobs, uint32_t njobs) {
+    constexpr int CAP = kSmallCap, ITEMS = CAP / kBlock;
+    __shared__ uint64_t s_key[CAP];
+    __shared__ uint16_t s_ia[CAP], s_ib[CAP];
+    __shared__ uint32_t s_cnt[kWaves * kBins];
+    __shared__ uint32_t s_bstart[kBins];
+    __shared__ uint32_t s_tmp[2 * kWaves];
+    __shared__ uint64_t s_red[2 * kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
+        const BatchSmallJob& J = jobs[jb];
+        const int r = J.r;
+        const uint32_t L = J.n;
+        CT c[R][ITEMS];
+        VT v[ITEMS];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            if (m >= r) break;
+            const CT* src = (const CT*)J.src_crd[m];
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t j = i * kBlock + tid;
+                c[m][i] = j < L ? src[j] : CT(0);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = i * kBlock + tid;
+            v[i] = j < L ? ((const VT*)J.src_val)[j] : VT(0);
+            s_ia[j] = (uint16_t)j;
+        }
+        uint16_t* cur = s_ia;
+        uint16_t* nxt = s_ib;
+        for (int q = 0; q < J.nsub; ++q) {
+            __syncthreads();
+            uint64_t kor = 0, kand = ~0ull;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t j = i * kBlock + tid;
+                uint64_t kv = 0;
+#pragma unroll
+                for (int m = 0; m < R; ++m)
+                    if (m < r && J.key[q].mask[m])
+                        kv |= (((uint64_t)c[m][i] >> J.key[q].src_lo[m]) & J.key[q].mask[m]) << J.key[q].dst[m];
+                s_key[j] = kv;
+                if (j < L) {
+                    kor |= kv;
+                    kand &= kv;
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                kor |= __shfl_xor(kor, o, 64);
+                kand &= __shfl_xor(kand, o, 64);
+            }
+            if (lane == 0) {
+                s_red[wave] = kor;
+                s_red[kWaves + wave] = kand;
+            }
+            __syncthreads();
+            kor = 0;
+            kand = ~0ull;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                kor |= s_red[w];
+                kand &= s_red[kWaves + w];
+            }
+            const uint64_t vary = kor ^ kand;
+            if (!vary) continue;
+            const int lo = __builtin_ctzll(vary), hi = 63 - __builtin_clzll(vary);
+            for (int sh = lo; sh <= hi; sh += 8) {
+                const int nb = min(8, hi - sh + 1);
+                const uint32_t dmask = (1u << nb) - 1u;
+                if (((vary >> sh) & dmask) == 0) continue;
+                for (int b = lane; b < kBins; b += 64) s_cnt[wave * kBins + b] = 0;
+                uint32_t dg[ITEMS], lp[ITEMS];
+                uint16_t sv[ITEMS];
+                const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t j = wb + i * 64;
+                    const bool ok = j < L;
+                    sv[i] = ok ? cur[j] : 0;
+                    dg[i] = ok ? (uint32_t)(s_key[sv[i]] >> sh) & dmask : 0;
+                }
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const bool ok = (wb + i * 64) < L;
+                    const uint32_t d = dg[i];
+                    uint64_t peers = ballot(ok);
+                    for (int b = 0; b < nb; ++b) {
+                        const bool bit = (d >> b) & 1u;
+                        const uint64_t bb = ballot(bit);
+                        peers &= bit ? bb : ~bb;
+                    }
+                    const uint32_t below = lanes_below(peers);
+                    uint32_t old = 0;
+                    if (ok) old = s_cnt[wave * kBins + d];
+                    lp[i] = old + below;
+                    if (ok && below == 0) s_cnt[wave * kBins + d] = old + (uint32_t)__popcll(peers);
+                }
+                __syncthreads();
+                {
+                    const uint32_t b = tid;
+                    uint32_t run = 0;
+#pragma unroll
+                    for (int w = 0; w < kWaves; ++w) {
+                        const uint32_t x = s_cnt[w * kBins + b];
+                        s_cnt[w * kBins + b] = run;
+                        run += x;
+                    }
+                    s_bstart[b] = block_excl_scan(run, s_tmp, nullptr);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    if ((wb + i * 64) < L) {
+                        const uint32_t d = dg[i];
+                        nxt[lp[i] + s_bstart[d] + s_cnt[wave * kBins + d]] = sv[i];
+                    }
+                }
+                __syncthreads();
+                uint16_t* tmp = cur;
+                cur = nxt;
+                nxt = tmp;
+            }
+        }
+        __syncthreads();
+        uint16_t pm[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) pm[i] = cur[i * kBlock + tid];
+#pragma unroll
+        for (int m = 0; m <= R; ++m) {
+            if (m < R && m >= r) continue;
+            __syncthreads();
+            if (m < R) {
+                CT* st = (CT*)s_key;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) st[i * kBlock + tid] = c[m][i];
+                __syncthreads();
+                CT* dst = (CT*)J.dst_crd[m];
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t j = i * kBlock + tid;
+                    if (j < L) dst[j] = st[pm[i]];
+                }
+            } else {
+                VT* st = (VT*)s_key;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) st[i * kBlock + tid] = v[i];
+                __syncthreads();
+                VT* dst = (VT*)J.dst_val;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t j = i * kBlock + tid;
+                    if (j < L) dst[j] = st[pm[i]];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------ validation
+
+template <typename CT>
+__global__ void __launch_bounds__(256) k_validate(ValidateArgs a) {
+    uint32_t bad = 0;
+    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < a.n; e += gridDim.x * kBlock) {
+        for (int m = 0; m < a.r; ++m) {
+            const int64_t c = (int64_t)((const CT*)a.crd[m])[e];
+            if (c < 0 || c >= a.ext[m]) bad |= 1u;
+        }
+        if (e > 0) {
+            int cmp = 0;
+            for (int i = 0; i < a.r && cmp == 0; ++i) {
+                const CT* p = (const CT*)a.crd[a.in_order[i]];
+                const int64_t x = (int64_t)p[e - 1], y = (int64_t)p[e];
+                cmp = (x < y) ? -1 : (x > y ? 1 : 0);
+            }
+            if (cmp > 0) bad |= 2u;
+        }
+    }
+    if (bad) atomicOr(a.flags, bad);
+}
+
+// ------------------------------------------------------------------------------ CSF pack
+
+// Fiber boundaries of levels 1..r-1 (prefix sigma_1..sigma_d changes), numbered with an
+// (r-1)-word look-back; level r is the identity.  Writes crd_d and pos_d.
+template <typename CT, typename PT>
+__global__ void __launch_bounds__(256) k_csf(CsfArgs a) {
+    constexpr int ITEMS = 8, TILE = kBlock * ITEMS;
+    __shared__ uint32_t s_wsum[8][kWaves];
+    __shared__ uint32_t s_excl[8];
+    __shared__ uint32_t s_t;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int L = a.r - 1;  // counted levels
+    if (tid == 0) s_t = atomicAdd(a.tile_counter, 1u);
+    __syncthreads();
+    const uint32_t t = s_t;
+    const uint32_t start = t * TILE;
+    if (start >= a.n) return;
+    const uint32_t len = min((uint32_t)TILE, a.n - start);
+    const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
+    // level of the first differing mode: records j with first-difference level <= d start
+    // a level-d fiber.  lev = 0 for the first record (every level starts).
+    uint8_t lev[ITEMS];
+    uint32_t wcnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t off = wb + i * 64;
+        // lev: first level whose mode differs from the previous record (r: none below r)
+        lev[i] = off < len ? (start + off == 0 ? 0 : (uint8_t)a.r) : 0xFF;
+    }
+    for (int d = L - 1; d >= 0; --d) {  // deepest level first, so the shallowest wins
+        const CT* p = (const CT*)a.crd[a.sigma[d]];
+        CT cur[ITEMS], prv[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t off = wb + i * 64;
+            const uint32_t e = start + off;
+            const bool ok = off < len && e > 0;
+            cur[i] = ok ? p[e] : CT(0);
+            prv[i] = ok ? p[e - 1] : CT(0);
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (lev[i] != 0xFF && lev[i] != 0 && cur[i] != prv[i]) lev[i] = (uint8_t)d;
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t off = wb + i * 64;
+        const int lv = lev[i];
+        for (int d = 0; d < L; ++d) wcnt[d] += (uint32_t)__popcll(ballot(off < len && lv <= d));
+    }
+    if (lane == 0)
+        for (int d = 0; d < L; ++d) s_wsum[d][wave] = wcnt[d];
+    __syncthreads();
+    if (tid < L) {
+        const int d = tid;
+        uint32_t tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += s_wsum[d][w];
+        uint32_t* st = a.status + (size_t)t * 8 + d;
+        uint32_t excl = 0;
+        if (t == 0) {
+            st_status(st, kFlagP | tot);
+        } else {
+            st_status(st, kFlagA | tot);
+            uint32_t j = t - 1, spins = 0;
+            for (;;) {
+                const uint32_t w = ld_status(&a.status[(size_t)j * 8 + d]);
+                const uint32_t f = w & ~kCntMask;
+                if (f == 0) {
+                    if (++spins > kSpinLimit) {
+                        atomicOr(a.err, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += w & kCntMask;
+                if (f == kFlagP) break;
+                --j;
+            }
+            st_status(st, kFlagP | (excl + tot));
+        }
+        s_excl[d] = excl;
+        if (start + len == a.n) a.fiber_counts[d + 1] = excl + tot;
+    }
+    if (tid == 0 && start + len == a.n) {
+        a.fiber_counts[0] = 1;
+        a.fiber_counts[a.r] = a.n;
+    }
+    __syncthreads();
+    // running fiber number per level for this thread's records
+    uint32_t base[8];
+    for (int d = 0; d < L; ++d) {
+        uint32_t b = s_excl[d];
+        for (int w = 0; w < wave; ++w) b += s_wsum[d][w];
+        base[d] = b;
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t off = wb + i * 64;
+        const uint32_t e = start + off;
+        const int lv = lev[i];
+        uint32_t fid[8];
+        for (int d = 0; d < L; ++d) {
+            const uint64_t m = ballot(off < len && lv <= d);
+            fid[d] = base[d] + lanes_below(m);  // fiber number if this record starts one
+            base[d] += (uint32_t)__popcll(m);
+        }
+        if (off < len) {
+            // level d (1-based) fiber starts here when lv <= d-1; leaves always start
+            for (int d = 1; d <= a.r; ++d) {
+                const bool starts = (d == a.r) || (lv <= d - 1);
+                if (!starts) continue;
+                const uint32_t f = (d == a.r) ? e : fid[d - 1];
+                ((CT*)a.out_crd[d - 1])[f] = ((const CT*)a.crd[a.sigma[d - 1]])[e];
+                // a new parent at level d-1 (or the root for d = 1) records its first child
+                if (d == 1) {
+                    if (e == 0) ((PT*)a.pos[0])[0] = 0;
+                } else if (lv <= d - 2) {
+                    ((PT*)a.pos[d - 1])[fid[d - 2]] = (PT)f;
+                }
+            }
+        }
+    }
+    if (tid == 0 && start + len == a.n) {
+        // closing offsets: pos_d[F_{d-1}] = F_d
+        ((PT*)a.pos[0])[1] = (PT)(L >= 1 ? (s_excl[0] + s_wsum[0][0] + s_wsum[0][1] + s_wsum[0][2] + s_wsum[0][3]) : a.n);
+        for (int d = 2; d <= a.r; ++d) {
+            const uint32_t fprev = s_excl[d - 2] + s_wsum[d - 2][0] + s_wsum[d - 2][1] + s_wsum[d - 2][2] + s_wsum[d - 2][3];
+            const uint32_t fcur = (d == a.r) ? a.n
+                : s_excl[d - 1] + s_wsum[d - 1][0] + s_wsum[d - 1][1] + s_wsum[d - 1][2] + s_wsum[d - 1][3];
+            ((PT*)a.pos[d - 1])[fprev] = (PT)fcur;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------ dispatch helpers
+
+template <typename K>
+int resident_blocks(K kernel) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess || per < 1) per = 1;
+    return per * device_cu_count();
+}
+
+template <int R, typename CT, typename VT, int ITEMS, int MODE>
+hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
+    auto kern = k_digit<R, CT, VT, ITEMS, MODE>;
+    static int resident = 0;
+    if (!resident) resident = resident_blocks(kern);
+    const uint32_t grid = (uint32_t)std::max(1, std::min<int>((int)a.ntiles, resident));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int R, typename CT, typename VT>
+hipError_t digit_r(const DigitArgs& a, int items, hipStream_t s) {
+    const int mode = a.seg_mode;
+    if (items == 16) {
+        if (mode == 2) return digit_rs<R, CT, VT, 16, 2>(a, s);
+        return mode ? digit_rs<R, CT, VT, 16, 1>(a, s) : digit_rs<R, CT, VT, 16, 0>(a, s);
+    }
+    if (mode == 2) return digit_rs<R, CT, VT, 8, 2>(a, s);
+    return mode ? digit_rs<R, CT, VT, 8, 1>(a, s) : digit_rs<R, CT, VT, 8, 0>(a, s);
+}
+
+}  // namespace
+}  // namespace qsd

@@ -61,23 +61,22 @@ void alg3(int r, const int* in_order, const int* target, std::vector<Call>* call
     }
 }
 
-void split_digits(Group& g, const PlanData& p) {
+int split_keys(const std::vector<int>& keys, const int* bits, int radix_bits, std::vector<SubKey>* subs) {
     // composite layout: the least significant key mode sits at bit 0
     int lo[kMaxR] = {}, w[kMaxR] = {};
     int shift = 0;
-    for (int i = (int)g.keys.size() - 1; i >= 0; --i) {
-        const int m = g.keys[i];
+    for (int i = (int)keys.size() - 1; i >= 0; --i) {
+        const int m = keys[i];
         lo[m] = shift;
-        w[m] = p.bits[m];
-        shift += p.bits[m];
+        w[m] = bits[m];
+        shift += bits[m];
     }
-    g.key_bits = shift;
-    g.subs.clear();
+    subs->clear();
     for (int c0 = 0; c0 < shift; c0 += 64) {
         const int c1 = std::min(shift, c0 + 64);
         SubKey sk{};
         std::memset(&sk.key, 0, sizeof(sk.key));
-        for (int m : g.keys) {
+        for (int m : keys) {
             const int a = lo[m], b = lo[m] + w[m];
             const int s = std::max(a, c0), e = std::min(b, c1);
             if (e > s) {
@@ -88,7 +87,7 @@ void split_digits(Group& g, const PlanData& p) {
         }
         sk.key.bits = c1 - c0;
         const int B = c1 - c0;
-        const int D = (B + p.radix_bits - 1) / p.radix_bits;
+        const int D = (B + radix_bits - 1) / radix_bits;
         const int base = B / D, extra = B % D;
         int at = 0;
         for (int d = 0; d < D; ++d) {
@@ -96,8 +95,13 @@ void split_digits(Group& g, const PlanData& p) {
             sk.passes.push_back(PassSpec{at, wd});
             at += wd;
         }
-        g.subs.push_back(sk);
+        subs->push_back(sk);
     }
+    return shift;
+}
+
+void split_digits(Group& g, const PlanData& p) {
+    g.key_bits = split_keys(g.keys, p.bits, p.radix_bits, &g.subs);
     if (!g.subs.empty()) g.local_key = g.subs[0].key;
 }
 
@@ -129,6 +133,24 @@ bool make_group(PlanData& p, RawGroup raw, std::vector<Group>* out) {
 }
 
 }  // namespace
+
+std::vector<SubKey> make_subkeys(const std::vector<int>& keys, const int* bits, int radix_bits) {
+    std::vector<SubKey> subs;
+    split_keys(keys, bits, radix_bits, &subs);
+    return subs;
+}
+
+std::vector<int> flattened_key(int r, const int* in_order, const int* out_order, const int* bits) {
+    int pos[kMaxR];
+    for (int i = 0; i < r; ++i) pos[in_order[i]] = i;
+    int q = r - 1;  // first mode of the in-order tail; a single last mode always is
+    while (q - 1 >= 0 && pos[out_order[q - 1]] < pos[out_order[q]]) --q;
+    if (r == 0) q = 0;
+    std::vector<int> keys;
+    for (int i = 0; i < q; ++i)
+        if (bits[out_order[i]] > 0) keys.push_back(out_order[i]);
+    return keys;
+}
 
 std::vector<Call> quesadilla_calls(int r, const int* in_order, const int* out_order) {
     std::vector<Call> calls;

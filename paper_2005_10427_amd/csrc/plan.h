@@ -85,4 +85,12 @@ bool build_plan(PlanData& p, int sched);
 
 std::string describe(const PlanData& p);
 
+// Digit passes of one composite key: `keys` most significant first, `bits` indexed by mode.
+// Sub-keys of at most 64 bits, least significant first; digits of at most radix_bits.
+std::vector<SubKey> make_subkeys(const std::vector<int>& keys, const int* bits, int radix_bits);
+
+// The flattened key of a transposition: sigma_1..sigma_q where sigma_{q+1}..sigma_r is the
+// longest tail of sigma already in input order; modes of extent 1 are dropped.
+std::vector<int> flattened_key(int r, const int* in_order, const int* out_order, const int* bits);
+
 }  // namespace qsd

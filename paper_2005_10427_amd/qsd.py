@@ -31,6 +31,15 @@ class qsd_desc(ctypes.Structure):
                 ("out_order", ctypes.POINTER(ctypes.c_int32)), ("flags", ctypes.c_uint32)]
 
 
+class qsd_batch_io(ctypes.Structure):
+    _fields_ = [("in_crd", ctypes.c_void_p * 8), ("in_val", ctypes.c_void_p),
+                ("out_crd", ctypes.c_void_p * 8), ("out_val", ctypes.c_void_p)]
+
+
+class qsd_tuning(ctypes.Structure):
+    _fields_ = [("items", ctypes.c_int32), ("radix_bits", ctypes.c_int32), ("small_cap", ctypes.c_int32)]
+
+
 class qsd_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -64,9 +73,26 @@ def load():
                                      ctypes.POINTER(ctypes.c_int32)]
     lib.qsd_status_str.argtypes = [ctypes.c_int]
     lib.qsd_status_str.restype = ctypes.c_char_p
+    lib.qsd_batch_plan.argtypes = [ctypes.POINTER(qsd_desc), ctypes.c_int32, ctypes.POINTER(_VP)]
+    lib.qsd_batch_destroy.argtypes = [_VP]
+    lib.qsd_batch_destroy.restype = None
+    lib.qsd_batch_set_tuning.argtypes = [_VP, ctypes.POINTER(qsd_tuning)]
+    lib.qsd_batch_get_tuning.argtypes = [_VP, ctypes.POINTER(qsd_tuning)]
+    lib.qsd_batch_workspace.argtypes = [_VP, ctypes.POINTER(ctypes.c_size_t)]
+    lib.qsd_batch_workspace_max.argtypes = [_VP, ctypes.POINTER(ctypes.c_size_t)]
+    lib.qsd_batch_bind.argtypes = [_VP, ctypes.POINTER(qsd_batch_io), _VP, ctypes.c_size_t, _VP]
+    lib.qsd_batch_transpose.argtypes = [_VP, _VP, ctypes.c_size_t, _VP]
+    lib.qsd_batch_tune.argtypes = [_VP, ctypes.POINTER(qsd_batch_io), _VP, ctypes.c_size_t, _VP, ctypes.c_int32,
+                                   ctypes.POINTER(qsd_tuning), ctypes.POINTER(ctypes.c_float)]
+    lib.qsd_batch_graph.argtypes = [_VP, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]
+    lib.qsd_graph_launch.argtypes = [_VP, _VP]
+    lib.qsd_graph_destroy.argtypes = [_VP]
+    lib.qsd_graph_destroy.restype = None
     for name in ("qsd_plan", "qsd_plan_workspace", "qsd_plan_describe", "qsd_transpose",
                  "qsd_csf_workspace", "qsd_pack_csf", "qsd_device_status", "qsd_profile_start",
-                 "qsd_profile_stop"):
+                 "qsd_profile_stop", "qsd_batch_plan", "qsd_batch_set_tuning", "qsd_batch_get_tuning",
+                 "qsd_batch_workspace", "qsd_batch_workspace_max", "qsd_batch_bind", "qsd_batch_transpose",
+                 "qsd_batch_tune", "qsd_batch_graph", "qsd_graph_launch"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -89,15 +115,19 @@ def _ptrs(seq):
 def qsd_plan(order, nnz, extents, crd_type, val_type, in_order, out_order, sched="minimal", flags=0):
     """Returns an opaque plan handle (int)."""
     lib = load()
-    r = int(order)
-    ext = (ctypes.c_int64 * max(r, 1))(*[int(x) for x in extents])
-    ino = (ctypes.c_int32 * max(r, 1))(*[int(x) for x in in_order])
-    outo = (ctypes.c_int32 * max(r, 1))(*[int(x) for x in out_order])
-    d = qsd_desc(r, int(nnz), ext, int(crd_type), int(val_type), ino, outo, int(flags))
+    d, _keep = _desc(order, nnz, extents, crd_type, val_type, in_order, out_order, flags)
     h = _VP()
     _check(lib.qsd_plan(ctypes.byref(d), SCHED[sched] if isinstance(sched, str) else int(sched),
                         ctypes.byref(h)), "qsd_plan")
     return h.value
+
+
+def _desc(order, nnz, extents, crd_type, val_type, in_order, out_order, flags=0):
+    r = int(order)
+    ext = (ctypes.c_int64 * max(r, 1))(*[int(x) for x in extents])
+    ino = (ctypes.c_int32 * max(r, 1))(*[int(x) for x in in_order])
+    outo = (ctypes.c_int32 * max(r, 1))(*[int(x) for x in out_order])
+    return qsd_desc(r, int(nnz), ext, int(crd_type), int(val_type), ino, outo, int(flags)), (ext, ino, outo)
 
 
 def qsd_plan_destroy(plan):
@@ -149,6 +179,91 @@ def qsd_profile_stop():
     n = ctypes.c_int32()
     _check(load().qsd_profile_stop(out, 32, ctypes.byref(n)), "qsd_profile_stop")
     return {out[i].name.decode(): (out[i].launches, out[i].total_ms, out[i].bytes) for i in range(n.value)}
+
+
+def qsd_batch_plan(tensors):
+    """tensors: sequence of (order, nnz, extents, crd_type, val_type, in_order, out_order).
+    Returns an opaque batch handle (int)."""
+    keep = []
+    arr = (qsd_desc * max(len(tensors), 1))()
+    for i, t in enumerate(tensors):
+        d, k = _desc(*t)
+        arr[i] = d
+        keep.append(k)
+    h = _VP()
+    _check(load().qsd_batch_plan(arr, len(tensors), ctypes.byref(h)), "qsd_batch_plan")
+    return h.value
+
+
+def qsd_batch_destroy(batch):
+    load().qsd_batch_destroy(batch)
+
+
+def qsd_batch_set_tuning(batch, items, radix_bits, small_cap):
+    t = qsd_tuning(int(items), int(radix_bits), int(small_cap))
+    _check(load().qsd_batch_set_tuning(batch, ctypes.byref(t)), "qsd_batch_set_tuning")
+
+
+def qsd_batch_get_tuning(batch):
+    t = qsd_tuning()
+    _check(load().qsd_batch_get_tuning(batch, ctypes.byref(t)), "qsd_batch_get_tuning")
+    return t.items, t.radix_bits, t.small_cap
+
+
+def qsd_batch_workspace(batch):
+    n = ctypes.c_size_t()
+    _check(load().qsd_batch_workspace(batch, ctypes.byref(n)), "qsd_batch_workspace")
+    return n.value
+
+
+def qsd_batch_workspace_max(batch):
+    n = ctypes.c_size_t()
+    _check(load().qsd_batch_workspace_max(batch, ctypes.byref(n)), "qsd_batch_workspace_max")
+    return n.value
+
+
+def _ios(ios):
+    """ios: sequence of (in_crd ptrs, in_val ptr, out_crd ptrs, out_val ptr)."""
+    arr = (qsd_batch_io * max(len(ios), 1))()
+    for i, (ic, iv, oc, ov) in enumerate(ios):
+        for m, p in enumerate(ic):
+            arr[i].in_crd[m] = p
+        for m, p in enumerate(oc):
+            arr[i].out_crd[m] = p
+        arr[i].in_val = iv
+        arr[i].out_val = ov
+    return arr
+
+
+def qsd_batch_bind(batch, ios, ws, ws_bytes, stream):
+    _check(load().qsd_batch_bind(batch, _ios(ios), ws, int(ws_bytes), stream), "qsd_batch_bind")
+
+
+def qsd_batch_transpose(batch, ws, ws_bytes, stream):
+    _check(load().qsd_batch_transpose(batch, ws, int(ws_bytes), stream), "qsd_batch_transpose")
+
+
+def qsd_batch_tune(batch, ios, ws, ws_bytes, stream, reps=3):
+    """Returns ((items, radix_bits, small_cap), best_ms)."""
+    t = qsd_tuning()
+    ms = ctypes.c_float()
+    _check(load().qsd_batch_tune(batch, _ios(ios), ws, int(ws_bytes), stream, int(reps), ctypes.byref(t),
+                                 ctypes.byref(ms)), "qsd_batch_tune")
+    return (t.items, t.radix_bits, t.small_cap), ms.value
+
+
+def qsd_batch_graph(batch, ws, ws_bytes):
+    h = _VP()
+    _check(load().qsd_batch_graph(batch, ws, int(ws_bytes), ctypes.byref(h)), "qsd_batch_graph")
+    return h.value
+
+
+def qsd_graph_launch(graph, stream):
+    _check(load().qsd_graph_launch(graph, stream), "qsd_graph_launch")
+
+
+def qsd_graph_destroy(graph):
+    load().qsd_graph_destroy(graph)
 
 
 def qsd_status_str(code):
@@ -238,3 +353,77 @@ class Plan:
         pos = [pos[d][: counts[d] + 1] for d in range(self.r)]
         crd = [crd[d][: counts[d + 1]] for d in range(self.r)]
         return pos, crd, counts
+
+
+class Batch:
+    """Many transpositions in a few launches (optionally one HIP graph), on torch tensors.
+
+    tensors: list of dicts with keys crd (list of r device tensors), val, extents,
+    in_order, out_order.  Output tensors are allocated once and reused by every call."""
+
+    def __init__(self, tensors, device="cuda"):
+        import torch
+        self.torch = torch
+        self.tensors = tensors
+        ct = QSD_I64 if tensors and tensors[0]["crd"][0].dtype == torch.int64 else QSD_I32
+        vt = QSD_F64 if tensors and tensors[0]["val"].dtype == torch.float64 else QSD_F32
+        descs = [(len(t["crd"]), int(t["val"].shape[0]), t["extents"], ct, vt, t["in_order"], t["out_order"])
+                 for t in tensors]
+        self.handle = qsd_batch_plan(descs)
+        self.out_crd = [[torch.empty_like(c) for c in t["crd"]] for t in tensors]
+        self.out_val = [torch.empty_like(t["val"]) for t in tensors]
+        self.ws_bytes = qsd_batch_workspace_max(self.handle)
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+        self.graph = None
+        self.bind()
+
+    def __del__(self):
+        g = getattr(self, "graph", None)
+        if g:
+            try:
+                qsd_graph_destroy(g)
+            except Exception:
+                pass
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                qsd_batch_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def _io(self):
+        return [([c.data_ptr() for c in t["crd"]], t["val"].data_ptr(), [c.data_ptr() for c in oc], ov.data_ptr())
+                for t, oc, ov in zip(self.tensors, self.out_crd, self.out_val)]
+
+    def _stream(self, stream):
+        return (stream if stream is not None else self.torch.cuda.current_stream()).cuda_stream
+
+    def bind(self, stream=None):
+        qsd_batch_bind(self.handle, self._io(), self.ws.data_ptr(), self.ws_bytes, self._stream(stream))
+
+    def set_tuning(self, items, radix_bits, small_cap, stream=None):
+        qsd_batch_set_tuning(self.handle, items, radix_bits, small_cap)
+        self.bind(stream)
+
+    def tuning(self):
+        return qsd_batch_get_tuning(self.handle)
+
+    def tune(self, reps=3, stream=None):
+        return qsd_batch_tune(self.handle, self._io(), self.ws.data_ptr(), self.ws_bytes, self._stream(stream), reps)
+
+    def transpose(self, stream=None):
+        qsd_batch_transpose(self.handle, self.ws.data_ptr(), self.ws_bytes, self._stream(stream))
+        return self.out_crd, self.out_val
+
+    def capture(self):
+        if self.graph:
+            qsd_graph_destroy(self.graph)
+        self.graph = qsd_batch_graph(self.handle, self.ws.data_ptr(), self.ws_bytes)
+
+    def replay(self, stream=None):
+        qsd_graph_launch(self.graph, self._stream(stream))
+        return self.out_crd, self.out_val
+
+    def device_status(self, stream=None):
+        return qsd_device_status(self.ws.data_ptr(), self._stream(stream))
