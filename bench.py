@@ -1,6 +1,6 @@
 """Benchmark: transposed nonzeros per second on one MI355X.
 
-Workload (one step): the 3-mode tensor with extents 500000 x 20000 x 2000000, 1e8 distinct
+Default workload ("plain"; one step): the 3-mode tensor with extents 500000 x 20000 x 2000000, 1e8 distinct
 nonzeros whose coordinates are Zipf(1.1) over a relabelled extent, int32 coordinates, fp64
 values, input order (0,1,2), transposed to all five other orders.  Inputs are resident in
 device memory before the timed region; value = 5e8 * steps / seconds.
@@ -8,6 +8,12 @@ device memory before the timed region; value = 5e8 * steps / seconds.
 Also reported: the roofline of the dominant kernel (the digit pass), timed with HIP events
 recorded by the library on the stream each launch runs on, and the CPU oracle timed on a
 bounded sample of the same workload.
+
+``--workload batched``: 4,096 independent tensors (order 3 or 4, nnz log-uniform in
+[1e3, 1e6], extents log-uniform in [10, 1e6], Zipf exponents uniform in [0, 1.5], fp64
+values, random input and requested orders); one step is one replay of the autotuned,
+graph-captured batched transposition, compared with the same transpositions issued one by
+one with the minimal-pass plan.
 """
 import argparse
 import hashlib
@@ -22,7 +28,8 @@ sys.path.insert(0, ROOT)
 METRIC = "transposed nnz/s & HBM GB/s (% of peak); learned+batched vs plain schedule"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_digit_plain_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2005_10427_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2005_10427_amd", "csrc")
+KERNEL_SRCS = ["kernels_impl.h", "kernels.h", "kernels.hip"]
 
 
 def log(*a):
@@ -30,8 +37,12 @@ def log(*a):
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """Hash of the device-code sources (the counters are valid for exactly this code)."""
+    h = hashlib.sha256()
+    for name in KERNEL_SRCS:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic():
@@ -78,6 +89,11 @@ def main():
     ap.add_argument("--sched", default="minimal", choices=["minimal", "top2", "lsd", "auto"])
     ap.add_argument("--nnz", type=int, default=None, help="shrink the workload (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="plain", choices=["plain", "batched"])
+    ap.add_argument("--count", type=int, default=None, help="tensors of the batched workload (testing only)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="K",
+                    help="after timing, run K identity transpositions (plain copies of every array) "
+                         "that calibrate hardware byte counters against a known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU path is "
@@ -93,6 +109,8 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         return 1
+    if args.workload == "batched":
+        return bench_batched(args)
     cfg = CONFIGS["plain"]
     sigmas = cfg["sigmas"]
     log("generating workload ...")
@@ -161,10 +179,127 @@ def main():
         "roofline": roofline,
         "modelled_bytes_per_step": whole_bytes / args.steps,
     }
+    if args.copy_probe:
+        ident = qsd.Plan(T.extents, T.in_order, T.in_order, N, "int32", "float64", args.sched)
+        oc, ov = outs[0]
+        for _ in range(args.copy_probe):
+            ident.transpose(crd, val, oc, ov, stream=stream, ws=ws)
+        torch.cuda.synchronize()
+        out["copy_probe"] = {"launches_per_call": T.order + 1,
+                             "bytes_per_crd_copy": 2 * N * 4, "bytes_per_val_copy": 2 * N * 8}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(T, sigmas)
     print(json.dumps(out), flush=True)
+    return 0
+
+
+def cpu_baseline_batched(T, budget_s=20.0):
+    """The oracle on the first tensors of the batch (copied to the host), single-threaded."""
+    from oracle.transpose import transpose as oracle_transpose
+    done, k, sec = 0, 0, 0.0
+    while k < len(T) and sec < budget_s / 2:
+        crd = [c.cpu().numpy() for c in T[k].crd]
+        val = T[k].val.cpu().numpy()
+        t0 = time.perf_counter()
+        oracle_transpose(crd, val, T[k].out_order)
+        sec += time.perf_counter() - t0
+        done += T[k].nnz
+        k += 1
+    return {"value": done / sec, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {k} tensors of the batch ({done} nonzeros), {sec:.1f} s single-threaded "
+                      f"numpy (lexsort + gather)"}
+
+
+def bench_batched(args):
+    import torch
+    from datagen.batched import BATCHED, make_batch
+    from paper_2005_10427_amd import qsd
+
+    cfg = dict(BATCHED)
+    if args.count:
+        cfg["count"] = args.count
+    log(f"generating {cfg['count']} tensors on the GPU ...")
+    t0 = time.time()
+    T = make_batch(device="cuda", **cfg)
+    torch.cuda.synchronize()
+    N = sum(t.nnz for t in T)
+    log(f"generated {N} nonzeros in {time.time() - t0:.1f} s")
+    stream = torch.cuda.current_stream()
+
+    B = qsd.Batch([t.as_dict() for t in T])
+    best, best_ms = B.tune(reps=2)
+    log(f"autotuned items/radix/small_cap = {best}: {best_ms:.3f} ms")
+    B.capture()
+
+    # the same transpositions one by one with the minimal-pass plan (shared workspace)
+    plans = [qsd.Plan(t.extents, t.in_order, t.out_order, max(t.nnz, 1), "int32", "float64", "minimal")
+             for t in T]
+    ws = torch.empty(max(p.ws_bytes for p in plans), dtype=torch.uint8, device="cuda")
+    out = (B.out_crd, B.out_val)
+
+    def plain_step():
+        for i, (p, t) in enumerate(zip(plans, T)):
+            if t.nnz:
+                p.transpose(t.crd, t.val, out[0][i], out[1][i], stream=stream, ws=ws)
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    plain_sec = timed(plain_step, max(1, args.steps // 4))
+    log(f"plain sequence: {plain_sec * 1e3:.3f} ms/step, {N / plain_sec / 1e9:.2f} G nnz/s")
+    eager_sec = timed(lambda: B.transpose(stream), args.steps)
+    log(f"batched eager: {eager_sec * 1e3:.3f} ms/step")
+    sec = timed(lambda: B.replay(stream), args.steps)
+    value = N / sec
+    log(f"batched graph: {sec * 1e3:.3f} ms/step, {value / 1e9:.2f} G nnz/s")
+    if B.device_status():
+        log("device status nonzero")
+        return 1
+
+    # roofline of the dominant kernel, from library-recorded events over eager batched steps
+    qsd.qsd_profile_start()
+    for _ in range(args.steps):
+        B.transpose(stream)
+    torch.cuda.synchronize()
+    prof = qsd.qsd_profile_stop()
+    for k, (n_l, ms, b) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        log(f"  {k:12s} launches={n_l:6d} total={ms:9.3f} ms avg={ms / max(n_l, 1) * 1e3:8.1f} us"
+            + (f"  {b / ms / 1e6:8.1f} GB/s" if b and ms else ""))
+    n_l, ms, b = prof["digit_batch"]
+    avg_s = ms / n_l / 1e3
+    achieved = b / n_l / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_digit (batched digit pass)", "launches": n_l,
+                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": b / n_l}
+    res = {
+        "metric": METRIC, "value": value, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "batched: 4096 tensors of order 3 or 4, nnz log-uniform in [1e3, 1e6], "
+                               "extents log-uniform in [10, 1e6], Zipf s uniform in [0, 1.5], int32 "
+                               "coordinates, fp64 values, random input and output orders; one graph "
+                               "replay per step",
+                   "tensors": len(T), "nnz": N, "tuning": {"items": best[0], "radix_bits": best[1],
+                                                           "small_cap": best[2]}},
+        "plain_sequence": {"value": N / plain_sec, "ms_per_step": plain_sec * 1e3,
+                           "schedule": "minimal", "launch": "one qsd_transpose per tensor"},
+        "batched_eager_ms_per_step": eager_sec * 1e3,
+        "speedup_vs_plain_sequence": plain_sec / sec,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample ...")
+        res["cpu_baseline"] = cpu_baseline_batched(T)
+    print(json.dumps(res), flush=True)
     return 0
 
 
