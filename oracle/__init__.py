@@ -19,10 +19,14 @@ Contents (each function cites the paper passage it restates):
                        coordinate tuples, and a plan executor built on them.
 * ``csf``           -- compressed-sparse-fiber packing of a sigma-sorted COO
                        tensor and its expansion back to COO.
-* ``mlp``           -- fp64 forward/backward/Adam of the schedule-selector MLP.
+* ``mlp``           -- fp64 forward/backward/Adam of the schedule-selector MLP
+                       (the true-cost model the paper proposes in Sec. 6).
+* ``features``      -- the selector's 32 features: sampled counts per mode and
+                       the pass/bit counts of the three schedules.
 * ``invariants``    -- checks that hold for any correct transposition.
 
 Parity status: every function above is pinned by tests that do not re-type its
 formula (worked example of Sec. 3.3, brute-force enumeration, closed forms,
-the pass-count figure of Sec. 4.2, finite differences for the MLP).
+the pass-count figure of Sec. 4.2, finite differences for the MLP, published
+SplitMix64 outputs, brute-force recounts of the feature counts).
 """
