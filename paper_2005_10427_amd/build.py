@@ -14,8 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqsd.so")
 
-SOURCES = ["api.cpp", "plan.cpp", "kernels.hip", "digit_u32_u64.hip", "digit_u32_u32.hip",
-           "digit_u64_u64.hip", "digit_u64_u32.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "select.cpp", "kernels.hip", "select_kernels.hip", "digit_u32_u64.hip",
+           "digit_u32_u32.hip", "digit_u64_u64.hip", "digit_u64_u32.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -144,6 +144,15 @@ qsd_status check_desc(const qsd_desc* d) {
     return QSD_OK;
 }
 
+}  // namespace
+
+// Argument check shared with the selector's entry points.
+namespace qsd {
+qsd_status desc_status(const qsd_desc* d) { return check_desc(d); }
+}  // namespace qsd
+
+namespace {
+
 struct Bufs {
     const void* crd[kMaxR];
     const void* val;

@@ -88,6 +88,34 @@ def load():
     lib.qsd_graph_launch.argtypes = [_VP, _VP]
     lib.qsd_graph_destroy.argtypes = [_VP]
     lib.qsd_graph_destroy.restype = None
+    F = ctypes.POINTER(ctypes.c_float)
+    U32 = ctypes.POINTER(ctypes.c_uint32)
+    lib.qsd_select_workspace.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
+    lib.qsd_feature_counts.argtypes = [ctypes.POINTER(qsd_desc), ctypes.POINTER(_VP), _VP, ctypes.c_size_t, _VP,
+                                       U32, U32, U32]
+    lib.qsd_features.argtypes = [ctypes.POINTER(qsd_desc), ctypes.POINTER(_VP), _VP, ctypes.c_size_t, _VP, F]
+    lib.qsd_mlp_init.argtypes = [ctypes.c_uint64, F]
+    lib.qsd_mlp_forward.argtypes = [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP]
+    lib.qsd_mlp_backward_workspace.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.qsd_mlp_backward.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP, ctypes.c_size_t,
+                                     _VP]
+    lib.qsd_mlp_adam.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, _VP]
+    lib.qsd_mlp_train_workspace.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.qsd_mlp_train.argtypes = [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                  ctypes.c_uint64, _VP, ctypes.c_size_t, _VP, F]
+    lib.qsd_model_create.argtypes = [F, ctypes.c_float, ctypes.POINTER(_VP)]
+    lib.qsd_model_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(_VP)]
+    lib.qsd_model_destroy.argtypes = [_VP]
+    lib.qsd_model_destroy.restype = None
+    lib.qsd_select.argtypes = [_VP, ctypes.POINTER(qsd_desc), ctypes.POINTER(_VP), _VP, ctypes.c_size_t, _VP,
+                               ctypes.POINTER(ctypes.c_int), F]
+    lib.qsd_plan_auto.argtypes = [_VP, ctypes.POINTER(qsd_desc), ctypes.POINTER(_VP), _VP, ctypes.c_size_t, _VP,
+                                  ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int)]
+    for name in ("qsd_select_workspace", "qsd_feature_counts", "qsd_features", "qsd_mlp_init", "qsd_mlp_forward",
+                 "qsd_mlp_backward_workspace", "qsd_mlp_backward", "qsd_mlp_adam", "qsd_mlp_train_workspace",
+                 "qsd_mlp_train", "qsd_model_create", "qsd_model_load", "qsd_select", "qsd_plan_auto"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("qsd_plan", "qsd_plan_workspace", "qsd_plan_describe", "qsd_transpose",
                  "qsd_csf_workspace", "qsd_pack_csf", "qsd_device_status", "qsd_profile_start",
                  "qsd_profile_stop", "qsd_batch_plan", "qsd_batch_set_tuning", "qsd_batch_get_tuning",
@@ -264,6 +292,119 @@ def qsd_graph_launch(graph, stream):
 
 def qsd_graph_destroy(graph):
     load().qsd_graph_destroy(graph)
+
+
+NFEAT, NSCHED, MLP_NPARAM, FEAT_COUNTS = 32, 3, 6467, 3 * (MAX_ORDER + 2)
+SCHED_NAMES = {1: "minimal", 2: "top2", 3: "lsd"}
+
+
+def qsd_select_workspace():
+    n = ctypes.c_size_t()
+    _check(load().qsd_select_workspace(ctypes.byref(n)), "qsd_select_workspace")
+    return n.value
+
+
+def qsd_feature_counts(desc, in_crd, ws, ws_bytes, stream):
+    """desc: (order, nnz, extents, crd_type, val_type, in_order, out_order).
+    Returns (counts list of FEAT_COUNTS ints, S, pairs)."""
+    d, _keep = _desc(*desc)
+    out = (ctypes.c_uint32 * FEAT_COUNTS)()
+    S, P = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(load().qsd_feature_counts(ctypes.byref(d), _ptrs(in_crd), ws, int(ws_bytes), stream, out,
+                                     ctypes.byref(S), ctypes.byref(P)), "qsd_feature_counts")
+    return list(out), S.value, P.value
+
+
+def qsd_features(desc, in_crd, ws, ws_bytes, stream):
+    d, _keep = _desc(*desc)
+    out = (ctypes.c_float * NFEAT)()
+    _check(load().qsd_features(ctypes.byref(d), _ptrs(in_crd), ws, int(ws_bytes), stream, out), "qsd_features")
+    return list(out)
+
+
+def qsd_mlp_init(seed):
+    out = (ctypes.c_float * MLP_NPARAM)()
+    _check(load().qsd_mlp_init(ctypes.c_uint64(int(seed)), out), "qsd_mlp_init")
+    return list(out)
+
+
+def qsd_mlp_forward(params, x, n, h1, h2, y, stream):
+    _check(load().qsd_mlp_forward(params, x, int(n), h1, h2, y, stream), "qsd_mlp_forward")
+
+
+def qsd_mlp_backward_workspace(n):
+    b = ctypes.c_size_t()
+    _check(load().qsd_mlp_backward_workspace(int(n), ctypes.byref(b)), "qsd_mlp_backward_workspace")
+    return b.value
+
+
+def qsd_mlp_backward(params, x, h1, h2, y, t, n, grad, loss, ws, ws_bytes, stream):
+    _check(load().qsd_mlp_backward(params, x, h1, h2, y, t, int(n), grad, loss, ws, int(ws_bytes), stream),
+           "qsd_mlp_backward")
+
+
+def qsd_mlp_adam(params, grad, m, v, step, lr, beta1, beta2, eps, stream):
+    _check(load().qsd_mlp_adam(params, grad, m, v, int(step), lr, beta1, beta2, eps, stream), "qsd_mlp_adam")
+
+
+def qsd_mlp_train_workspace(n, batch):
+    b = ctypes.c_size_t()
+    _check(load().qsd_mlp_train_workspace(int(n), int(batch), ctypes.byref(b)), "qsd_mlp_train_workspace")
+    return b.value
+
+
+def qsd_mlp_train(params, x, t, n, epochs, batch, lr, seed, ws, ws_bytes, stream):
+    loss = ctypes.c_float()
+    _check(load().qsd_mlp_train(params, x, t, int(n), int(epochs), int(batch), float(lr),
+                                ctypes.c_uint64(int(seed)), ws, int(ws_bytes), stream, ctypes.byref(loss)),
+           "qsd_mlp_train")
+    return loss.value
+
+
+def qsd_model_create(params, margin):
+    arr = (ctypes.c_float * MLP_NPARAM)(*[float(x) for x in params])
+    h = _VP()
+    _check(load().qsd_model_create(arr, float(margin), ctypes.byref(h)), "qsd_model_create")
+    return h.value
+
+
+def qsd_model_load(path):
+    h = _VP()
+    _check(load().qsd_model_load(os.fsencode(path), ctypes.byref(h)), "qsd_model_load")
+    return h.value
+
+
+def qsd_model_destroy(model):
+    load().qsd_model_destroy(model)
+
+
+def qsd_select(model, desc, in_crd, ws, ws_bytes, stream):
+    """Returns (chosen schedule code, predicted log2 ms of the three schedules)."""
+    d, _keep = _desc(*desc)
+    ch = ctypes.c_int()
+    pred = (ctypes.c_float * NSCHED)()
+    _check(load().qsd_select(model, ctypes.byref(d), _ptrs(in_crd), ws, int(ws_bytes), stream, ctypes.byref(ch),
+                             pred), "qsd_select")
+    return ch.value, list(pred)
+
+
+def qsd_plan_auto(model, desc, in_crd, ws, ws_bytes, stream):
+    """Returns (plan handle, chosen schedule code)."""
+    d, _keep = _desc(*desc)
+    h = _VP()
+    ch = ctypes.c_int()
+    _check(load().qsd_plan_auto(model, ctypes.byref(d), _ptrs(in_crd), ws, int(ws_bytes), stream,
+                                ctypes.byref(h), ctypes.byref(ch)), "qsd_plan_auto")
+    return h.value, ch.value
+
+
+def write_model_file(path, params, margin):
+    """The selector weights file read by qsd_model_load."""
+    import struct
+    with open(path, "wb") as f:
+        f.write(b"QSDMLP1\0")
+        f.write(struct.pack("<if", MLP_NPARAM, float(margin)))
+        f.write(struct.pack(f"<{MLP_NPARAM}f", *[float(x) for x in params]))
 
 
 def qsd_status_str(code):

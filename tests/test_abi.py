@@ -142,3 +142,30 @@ def test_bad_arguments_are_rejected_before_launch(lib):
     finally:
         qsd.qsd_plan_destroy(h)
     assert qsd.qsd_status_str(7).startswith("workspace")
+
+
+def test_selector_host_parts(lib):
+    import numpy as np
+    from oracle import features as OF
+    from oracle import mlp as OM
+    # initial weights: same SplitMix64 stream and rounding as the oracle's
+    for seed in (0, 7, 2 ** 63 + 5):
+        assert np.array_equal(np.array(qsd.qsd_mlp_init(seed), dtype=np.float64), OM.init_params(seed))
+    # an empty request needs no device work: the features come from the plan terms alone
+    for tau, sigma in [((0, 1, 2), (0, 2, 1)), ((2, 0, 1, 3), (1, 3, 0, 2))]:
+        ext = (100, 9, 1000, 5)[:len(tau)]
+        f = qsd.qsd_features((len(tau), 0, ext, qsd.QSD_I32, qsd.QSD_F64, tau, sigma), [0] * len(tau), None, 0,
+                             None)
+        want = OF.features([np.zeros(0, np.int32)] * len(tau), ext, tau, sigma)
+        assert np.allclose(f, want, atol=1e-7)
+    with pytest.raises(qsd.QsdError) as e:  # workspace too small for a real request
+        qsd.qsd_features((3, 10, (4, 4, 4), qsd.QSD_I32, qsd.QSD_F64, (0, 1, 2), (2, 1, 0)), [0x1000] * 3, 0x1000,
+                         16, None)
+    assert e.value.code == 7
+    with pytest.raises(qsd.QsdError) as e:  # bad order
+        qsd.qsd_features((3, 10, (4, 4, 4), qsd.QSD_I32, qsd.QSD_F64, (0, 1, 1), (2, 1, 0)), [0x1000] * 3, 0x1000,
+                         4096, None)
+    assert e.value.code == 2
+    assert qsd.qsd_mlp_train_workspace(1000, 128) > 1000 * 4
+    with pytest.raises(qsd.QsdError):
+        qsd.qsd_mlp_train_workspace(10, 0)
