@@ -122,7 +122,11 @@ def main():
     dev = torch.device("cuda:0")
     crd = [torch.from_numpy(c).to(dev) for c in T.crd]
     val = torch.from_numpy(T.val).to(dev)
-    plans = [qsd.Plan(T.extents, T.in_order, s, N, "int32", "float64", args.sched) for s in sigmas]
+    model = qsd.qsd_model_load(qsd.MODEL_PATH) if args.sched == "auto" else None
+    plans = [qsd.Plan(T.extents, T.in_order, s, N, "int32", "float64", args.sched, model=model, crd=crd)
+             for s in sigmas]
+    if model is not None:
+        log("selector chose " + ", ".join(f"{s}: {qsd.SCHED_NAMES[p.chosen]}" for s, p in zip(sigmas, plans)))
     ws = torch.empty(max(p.ws_bytes for p in plans), dtype=torch.uint8, device=dev)
     outs = [([torch.empty_like(c) for c in crd], torch.empty_like(val)) for _ in sigmas]
     stream = torch.cuda.current_stream(dev)

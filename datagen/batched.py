@@ -136,6 +136,19 @@ def _tensor(spec, device, crd_dtype, val_dtype, torch):
                        out_order=spec["sigma"], zipf=spec["s"])
 
 
+def iter_batch(count, seed=BATCH_SEED, orders=(3, 4), nnz_range=(1e3, 1e6), ext_range=(10, 1e6), zipf_max=1.5,
+               device="cpu", crd_dtype="int32", val_dtype="float64", start=0):
+    """The tensors of make_batch(count, seed, ...) one at a time (index, tensor), from `start`
+    on, so that large collections never sit in memory together."""
+    import torch
+    rng = np.random.Generator(np.random.Philox(seed))
+    specs = _draw_params(rng, count, orders, nnz_range, ext_range, zipf_max)
+    cd = getattr(torch, crd_dtype)
+    vd = getattr(torch, val_dtype)
+    for i in range(start, count):
+        yield i, _tensor(specs[i], device, cd, vd, torch)
+
+
 def make_batch(count, seed=BATCH_SEED, orders=(3, 4), nnz_range=(1e3, 1e6), ext_range=(10, 1e6),
                zipf_max=1.5, device="cpu", crd_dtype="int32", val_dtype="float64", extra=()):
     """`count` tensors drawn as in the module recipe, then the fixed tensors in `extra`

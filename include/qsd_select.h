@@ -94,16 +94,19 @@ qsd_status qsd_mlp_train(float* params_dev, const float* x_dev, const float* t_d
 
 /* A trained selector.  params_host: QSD_MLP_NPARAM floats (copied to the device).  margin:
  * another schedule is chosen only when its predicted log2 time is below MINIMAL's by more
- * than margin.  qsd_model_load reads the file format written by the training tool:
- * 8 bytes "QSDMLP1\0", int32 nparam, float32 margin, float32 params[nparam] (little endian). */
+ * than margin (>= 0).  min_nnz: requests with fewer nonzeros take MINIMAL without sampling
+ * (the choice cannot pay for itself there).  qsd_model_load reads the file format written by
+ * the training tool (little endian): 8 bytes "QSDMLP1\0", int32 nparam, float32 margin,
+ * int64 min_nnz, float32 params[nparam]. */
 typedef struct qsd_model_s* qsd_model_t;
-qsd_status qsd_model_create(const float* params_host, float margin, qsd_model_t* out);
+qsd_status qsd_model_create(const float* params_host, float margin, int64_t min_nnz, qsd_model_t* out);
 qsd_status qsd_model_load(const char* path, qsd_model_t* out);
 void qsd_model_destroy(qsd_model_t model);
 
 /* Features + forward pass on the device, then the choice: MINIMAL unless another schedule is
- * predicted faster by more than the margin; MINIMAL too when a feature is not finite or
- * outside [0, 4].  predicted_host (3 floats) may be NULL.  Synchronises the stream. */
+ * predicted faster by more than the margin; MINIMAL too below the model's min_nnz (no device
+ * work then) and when a feature is not finite or outside [0, 4].  predicted_host (3 floats)
+ * may be NULL; it is left untouched when no prediction is made.  Synchronises the stream. */
 qsd_status qsd_select(qsd_model_t model, const qsd_desc* desc, const void* const* in_crd, void* ws,
                       size_t ws_bytes, hipStream_t stream, qsd_sched_t* chosen, float* predicted_host);
 

@@ -22,6 +22,7 @@ using namespace qsd;
 struct qsd_model_s {
     float* params = nullptr;  // device
     float margin = 0.f;
+    int64_t min_nnz = 0;
 };
 
 namespace {
@@ -348,13 +349,15 @@ qsd_status qsd_mlp_train(float* params_dev, const float* x_dev, const float* t_d
     return QSD_OK;
 }
 
-qsd_status qsd_model_create(const float* params_host, float margin, qsd_model_t* out) {
+qsd_status qsd_model_create(const float* params_host, float margin, int64_t min_nnz, qsd_model_t* out) {
     if (!params_host || !out) return QSD_ERR_NULL;
     *out = nullptr;
+    if (!std::isfinite(margin) || margin < 0.f || min_nnz < 0) return QSD_ERR_UNSUPPORTED;
     for (int i = 0; i < kNParam; ++i)
         if (!std::isfinite(params_host[i])) return QSD_ERR_UNSUPPORTED;
     auto* m = new qsd_model_s();
     m->margin = margin;
+    m->min_nnz = min_nnz;
     if (hipMalloc(&m->params, kNParam * sizeof(float)) != hipSuccess) {
         delete m;
         return QSD_ERR_HIP;
@@ -376,13 +379,14 @@ qsd_status qsd_model_load(const char* path, qsd_model_t* out) {
     char magic[8];
     int32_t np = 0;
     float margin = 0.f;
+    int64_t min_nnz = 0;
     std::vector<float> p(kNParam);
     const bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "QSDMLP1", 8) == 0 &&
                     std::fread(&np, 4, 1, f) == 1 && np == kNParam && std::fread(&margin, 4, 1, f) == 1 &&
-                    std::fread(p.data(), 4, kNParam, f) == (size_t)kNParam;
+                    std::fread(&min_nnz, 8, 1, f) == 1 && std::fread(p.data(), 4, kNParam, f) == (size_t)kNParam;
     std::fclose(f);
     if (!ok) return QSD_ERR_UNSUPPORTED;
-    return qsd_model_create(p.data(), margin, out);
+    return qsd_model_create(p.data(), margin, min_nnz, out);
 }
 
 void qsd_model_destroy(qsd_model_t m) {
@@ -394,10 +398,12 @@ void qsd_model_destroy(qsd_model_t m) {
 qsd_status qsd_select(qsd_model_t model, const qsd_desc* desc, const void* const* in_crd, void* ws, size_t ws_bytes,
                       hipStream_t stream, qsd_sched_t* chosen, float* predicted_host) {
     if (!model || !chosen) return QSD_ERR_NULL;
-    float feat[kNFeat];
-    qsd_status st = qsd_features(desc, in_crd, ws, ws_bytes, stream, feat);
+    qsd_status st = desc_status(desc);
     if (st != QSD_OK) return st;
     *chosen = QSD_SCHED_MINIMAL;
+    if (desc->nnz < model->min_nnz) return QSD_OK;  // too small for the choice to pay for itself
+    float feat[kNFeat];
+    if ((st = qsd_features(desc, in_crd, ws, ws_bytes, stream, feat)) != QSD_OK) return st;
     for (float v : feat)
         if (!std::isfinite(v) || v < 0.f || v > 4.f) return QSD_OK;  // outside the trained range
     if (!ws || ws_bytes < kWsBytes) return QSD_ERR_WORKSPACE;

@@ -7,6 +7,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqsd.so")
+MODEL_PATH = os.path.join(HERE, "selector", "selector_model.bin")  # the trained schedule selector
 
 QSD_OK = 0
 STATUS = {0: "ok", 1: "null", 2: "bad order", 3: "bad extent", 4: "too large", 5: "unsorted",
@@ -104,7 +105,7 @@ def load():
     lib.qsd_mlp_train_workspace.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
     lib.qsd_mlp_train.argtypes = [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                                   ctypes.c_uint64, _VP, ctypes.c_size_t, _VP, F]
-    lib.qsd_model_create.argtypes = [F, ctypes.c_float, ctypes.POINTER(_VP)]
+    lib.qsd_model_create.argtypes = [F, ctypes.c_float, ctypes.c_int64, ctypes.POINTER(_VP)]
     lib.qsd_model_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(_VP)]
     lib.qsd_model_destroy.argtypes = [_VP]
     lib.qsd_model_destroy.restype = None
@@ -361,10 +362,10 @@ def qsd_mlp_train(params, x, t, n, epochs, batch, lr, seed, ws, ws_bytes, stream
     return loss.value
 
 
-def qsd_model_create(params, margin):
+def qsd_model_create(params, margin, min_nnz=0):
     arr = (ctypes.c_float * MLP_NPARAM)(*[float(x) for x in params])
     h = _VP()
-    _check(load().qsd_model_create(arr, float(margin), ctypes.byref(h)), "qsd_model_create")
+    _check(load().qsd_model_create(arr, float(margin), int(min_nnz), ctypes.byref(h)), "qsd_model_create")
     return h.value
 
 
@@ -398,12 +399,12 @@ def qsd_plan_auto(model, desc, in_crd, ws, ws_bytes, stream):
     return h.value, ch.value
 
 
-def write_model_file(path, params, margin):
+def write_model_file(path, params, margin, min_nnz=0):
     """The selector weights file read by qsd_model_load."""
     import struct
     with open(path, "wb") as f:
         f.write(b"QSDMLP1\0")
-        f.write(struct.pack("<if", MLP_NPARAM, float(margin)))
+        f.write(struct.pack("<ifq", MLP_NPARAM, float(margin), int(min_nnz)))
         f.write(struct.pack(f"<{MLP_NPARAM}f", *[float(x) for x in params]))
 
 
@@ -417,7 +418,9 @@ class Plan:
     """A plan plus the torch plumbing to call it on CUDA (HIP) tensors."""
 
     def __init__(self, extents, in_order, out_order, nnz, crd_dtype="int32", val_dtype="float64",
-                 sched="minimal", flags=0):
+                 sched="minimal", flags=0, model=None, crd=None):
+        """sched="auto" with a selector `model` (qsd_model_load) and the input coordinates
+        `crd` (device tensors) chooses the schedule with qsd_plan_auto."""
         import torch
         self.torch = torch
         self.r = len(extents)
@@ -429,8 +432,16 @@ class Plan:
         self.val_dtype = getattr(torch, str(val_dtype).replace("torch.", ""))
         ct = QSD_I64 if self.crd_dtype == torch.int64 else QSD_I32
         vt = QSD_F64 if self.val_dtype == torch.float64 else QSD_F32
-        self.handle = qsd_plan(self.r, self.nnz, self.extents, ct, vt, self.in_order, self.out_order,
-                               sched, flags)
+        self.chosen = None
+        if sched == "auto" and model is not None:
+            sws = torch.empty(qsd_select_workspace(), dtype=torch.uint8, device=crd[0].device)
+            self.handle, self.chosen = qsd_plan_auto(
+                model, (self.r, self.nnz, self.extents, ct, vt, self.in_order, self.out_order),
+                [c.data_ptr() for c in crd], sws.data_ptr(), sws.numel(),
+                torch.cuda.current_stream(crd[0].device).cuda_stream)
+        else:
+            self.handle = qsd_plan(self.r, self.nnz, self.extents, ct, vt, self.in_order, self.out_order,
+                                   sched, flags)
         self.ws_bytes = qsd_plan_workspace(self.handle)
         self._ws = None
 
