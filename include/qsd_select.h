@@ -1,5 +1,5 @@
 /* libqsd schedule selector: the true-cost model the paper proposes in place of counting
- * passes (Sec. 6; Sec. 5 shows that the fewest passes are not always the fastest, e.g. with
+ * passes (Sec. 5; Sec. 4.2 shows that the fewest passes are not always the fastest, e.g. with
  * large extents).  A small network predicts the run time of each of the three schedules of
  * qsd_plan from 32 features of the request, and AUTO takes the fastest prediction.
  *

@@ -20,7 +20,7 @@ Contents (each function cites the paper passage it restates):
 * ``csf``           -- compressed-sparse-fiber packing of a sigma-sorted COO
                        tensor and its expansion back to COO.
 * ``mlp``           -- fp64 forward/backward/Adam of the schedule-selector MLP
-                       (the true-cost model the paper proposes in Sec. 6).
+                       (the true-cost model the paper proposes in Sec. 5).
 * ``features``      -- the selector's 32 features: sampled counts per mode and
                        the pass/bit counts of the three schedules.
 * ``invariants``    -- checks that hold for any correct transposition.

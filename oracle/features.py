@@ -2,7 +2,7 @@
 
 The features describe what the paper identifies as the drivers of run time: how many
 passes a plan makes and how many of them are bucketed (Sec. 3.4-3.6, Sec. 5), the bit widths
-of the sorted modes (large extents make the count arrays large, Sec. 5), and the structure
+of the sorted modes (large extents make the count arrays large, Sec. 4.2), and the structure
 of the data (how many distinct values a mode takes, how skewed it is, and how often it
 changes between neighbouring nonzeros of the input, which sets the bucket sizes of
 Alg. 2).

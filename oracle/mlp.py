@@ -1,8 +1,8 @@
 """Oracle: the schedule selector's multilayer perceptron in float64.  TEST INFRASTRUCTURE ONLY.
 
 The paper observes that the minimal number of passes is not always the fastest plan and
-proposes minimising a model of the true cost instead (Sec. 6, future work; Sec. 5 on the
-effect of large extents).  The selector realises that model as a small fully connected
+proposes minimising a model of the true cost instead (Sec. 5; Sec. 4.2 on the effect of
+large extents).  The selector realises that model as a small fully connected
 network 32 -> 64 -> 64 -> 3 with ReLU after the two hidden layers, predicting the base-2
 logarithm of the run time (ms) of each of three schedules; it is trained by minimising the
 mean squared error with Adam (Kingma and Ba, "Adam: A Method for Stochastic Optimization",
