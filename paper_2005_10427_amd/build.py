@@ -32,31 +32,33 @@ CFLAGS = [
 ]
 
 
-def _compile(src, obj):
-    cmd = [HIPCC] + CFLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src, obj, extra=()):
+    cmd = [HIPCC] + CFLAGS + list(extra) + ["-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n" + res.stdout + res.stderr)
     return obj
 
 
-def build(verbose=False, jobs=None):
+def build(verbose=False, jobs=None, extra_flags=(), out=LIB):
+    """Compile every source and link `out` (the in-tree library by default); `extra_flags` are
+    added to every compile (e.g. -D overrides of tuning constants)."""
     jobs = jobs or min(len(SOURCES), max(1, os.cpu_count() or 1))
     with tempfile.TemporaryDirectory(prefix="qsd_build_") as tmp:
         objs = [os.path.join(tmp, os.path.splitext(s)[0] + ".o") for s in SOURCES]
         with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-            futs = [ex.submit(_compile, s, o) for s, o in zip(SOURCES, objs)]
+            futs = [ex.submit(_compile, s, o, extra_flags) for s, o in zip(SOURCES, objs)]
             for f in futs:
                 f.result()
-        out_tmp = LIB + ".tmp"
+        out_tmp = out + ".tmp"
         cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", out_tmp]
         if verbose:
             print(" ".join(cmd), flush=True)
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode != 0:
             raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
-    os.replace(out_tmp, LIB)
-    return LIB
+    os.replace(out_tmp, out)
+    return out
 
 
 if __name__ == "__main__":

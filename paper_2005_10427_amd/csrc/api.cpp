@@ -31,6 +31,7 @@ struct Layout {
     size_t status_words = 0;  // per array
     size_t seg_start = 0, region_seg = 0, bstatus = 0, bstatus_words = 0, med = 0, large = 0, seg_hist = 0;
     size_t tile_map = 0;
+    size_t pk[2] = {};        // packed-record ping-pong buffers (64-bit words)
     uint32_t max_large = 0, max_med = 0, max_tiles_large = 0;
     size_t total = 0;
 };
@@ -46,11 +47,40 @@ struct qsd_plan_s {
     Layout L;
     int tile = 0;
     int items = 16;
+    bool pack = true;                  // pack records inside global groups when they fit
     std::vector<size_t> sub_hist_off;  // word offset of each global sub-key's histograms
     int nseg_groups = 0;
 };
 
 namespace {
+
+// A global group of two or more digit passes moves packed records when every coordinate of a
+// nonzero fits in one 64-bit word: the first pass packs, the last unpacks (Sec. 5's bit
+// packing).  The group's composite key occupies the low bits of the word.
+bool packable(const qsd_plan_s* q, const Group& g) {
+    if (!q->pack || g.segmented || g.subs.size() != 1 || g.subs[0].passes.size() < 2) return false;
+    int total = 0;
+    for (int m = 0; m < q->p.r; ++m) total += q->p.bits[m];
+    if (total > 64) return false;
+    const KeySpec& k = g.subs[0].key;
+    for (int m = 0; m < q->p.r; ++m)
+        if (k.width[m] && (k.src_lo[m] != 0 || k.width[m] != q->p.bits[m])) return false;
+    return true;
+}
+
+void pack_spec(const PlanData& p, const KeySpec& k, DigitArgs& da) {
+    int at = k.bits;
+    for (int m = 0; m < p.r; ++m) {
+        const int b = p.bits[m];
+        da.pk_mask[m] = b ? ((b >= 64) ? ~0ull : ((1ull << b) - 1)) : 0;
+        if (k.width[m]) {
+            da.pk_pos[m] = k.dst[m];
+        } else {
+            da.pk_pos[m] = b ? at : 0;
+            at += b;
+        }
+    }
+}
 
 void make_layout(qsd_plan_s* q) {
     const PlanData& p = q->p;
@@ -58,6 +88,7 @@ void make_layout(qsd_plan_s* q) {
     const uint64_t N = (uint64_t)std::max<int64_t>(p.nnz, 1);
     int pref = 0;
     if (const char* e = std::getenv("QSD_DIGIT_ITEMS")) pref = std::atoi(e);  // tuning override
+    if (const char* e = std::getenv("QSD_PACK")) q->pack = std::atoi(e) != 0;   // tuning override
     q->items = digit_items(p.r, p.crd_bytes, p.val_bytes, pref);
     q->tile = kBlock * q->items;
     const uint64_t T = (uint64_t)q->tile;
@@ -119,6 +150,13 @@ void make_layout(qsd_plan_s* q) {
         L.seg_hist = at;
         at = up(at + (size_t)L.max_large * max_seg_passes * kBins * 4);
     }
+    bool any_pack = false;
+    for (const auto& g : p.groups) any_pack |= packable(q, g);
+    if (any_pack)
+        for (int i = 0; i < 2; ++i) {
+            L.pk[i] = at;
+            at = up(at + N * 8);
+        }
     L.total = at;
 }
 
@@ -392,16 +430,41 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
                 for (int m = 0; m < p.r; ++m) kmodes += key.mask[m] ? 1 : 0;
                 QSD_CK(timed(kHist, (double)n * p.crd_bytes * kmodes, stream,
                              [&] { return launch_hist(ha, p.r, p.crd_bytes, hgrid, stream); }));
+                const bool pk = packable(plan, g);
+                const double rec = p.r * p.crd_bytes + p.val_bytes, prec = 8.0 + p.val_bytes;
+                void* P[2] = {W + L.pk[0], W + L.pk[1]};
                 for (int i = 0; i < np; ++i) {
                     const Bufs dst = hop_dst(h);
                     DigitArgs da{};
+                    int r_launch = p.r, cb_launch = p.crd_bytes;
+                    double bytes = 2.0 * n * rec;
                     for (int m = 0; m < p.r; ++m) {
                         da.src_crd[m] = cur.crd[m];
                         da.dst_crd[m] = const_cast<void*>(dst.crd[m]);
                     }
+                    da.key = key;
+                    if (pk) {
+                        pack_spec(p, sk.key, da);
+                        if (i == 0) {  // coordinate arrays in, packed words out
+                            da.pk = 1;
+                            da.dst_crd[0] = P[0];
+                            bytes = n * (rec + prec);
+                        } else if (i + 1 < np) {  // packed words in and out: one 64-bit "mode"
+                            da = DigitArgs{};
+                            da.src_crd[0] = P[(i - 1) % 2];
+                            da.dst_crd[0] = P[i % 2];
+                            da.key.mask[0] = sk.key.bits >= 64 ? ~0ull : ((1ull << sk.key.bits) - 1);
+                            r_launch = 1;
+                            cb_launch = 8;
+                            bytes = 2.0 * n * prec;
+                        } else {  // packed words in, coordinate arrays out
+                            da.pk = 2;
+                            da.src_crd[0] = P[(i - 1) % 2];
+                            bytes = n * (rec + prec);
+                        }
+                    }
                     da.src_val = cur.val;
                     da.dst_val = const_cast<void*>(dst.val);
-                    da.key = key;
                     da.lo = sk.passes[i].lo;
                     da.bits = sk.passes[i].bits;
                     da.n = n;
@@ -412,8 +475,9 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
                     da.status_next = (i + 1 < np) ? S[(q + 1) % 2] : nullptr;
                     da.tile_counter = ctl + kCtlPassCnt + q;
                     da.err = ctl + kCtlErr;
-                    QSD_CK(timed(kDigit, 2.0 * n * (p.r * p.crd_bytes + p.val_bytes), stream,
-                                 [&] { return launch_digit(da, p.r, p.crd_bytes, p.val_bytes, plan->items, stream); }));
+                    QSD_CK(timed(kDigit, bytes, stream, [&] {
+                        return launch_digit(da, r_launch, cb_launch, p.val_bytes, plan->items, stream);
+                    }));
                     cur = dst;
                     ++h;
                     ++q;

@@ -82,6 +82,13 @@ struct DigitArgs {
     const uint32_t* tile_job;   // batch mode: tensor (table entry) of every stable tile
     const BatchPass* batch;     // batch mode: this launch's table
     uint32_t* err;
+    // Packed records (global mode only).  pk = 1: read the r coordinate arrays, write one
+    // array of 64-bit words sum_m (crd_m & pk_mask[m]) << pk_pos[m] (dst_crd[0]); pk = 2:
+    // read such words (src_crd[0]; the digit is taken from the word directly) and write the r
+    // coordinate arrays back.  pk = 0: records as given.
+    int32_t pk;
+    int32_t pk_pos[8];
+    uint64_t pk_mask[8];
 };
 
 // Upfront histograms of a batch: one job per (tensor, sub-key), a static tile range each.

@@ -219,7 +219,10 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
 
 // ------------------------------------------------------------------------------ digit pass
 
-constexpr int kLookWin = 8;
+#ifndef QSD_LOOK_WIN
+#define QSD_LOOK_WIN 8
+#endif
+constexpr int kLookWin = QSD_LOOK_WIN;
 
 // Decoupled look-back done by one whole wave for one counter: lane l reads the status of
 // tile j - l, so 64 predecessors are inspected per round trip.  Statuses are at
@@ -327,20 +330,29 @@ __device__ __forceinline__ void stage_items(T* sx, uint32_t len, uint32_t wb, co
         if (wb + i * 64 < len) sx[lp[i]] = x[i];
 }
 
+// Local slot j goes to global position s_base[digit of slot j] + j.
+__device__ __forceinline__ uint32_t slot_dest(const uint8_t* s_dig, const uint32_t* s_base, uint32_t j) {
+    return s_base[s_dig[j]] + j;
+}
+
 template <typename T, int ITEMS>
-__device__ __forceinline__ void drain_items(const T* sx, T* __restrict__ dst, uint32_t len,
-                                            const uint32_t (&gp)[ITEMS]) {
+__device__ __forceinline__ void drain_items(const T* sx, T* __restrict__ dst, uint32_t len, const uint8_t* s_dig,
+                                            const uint32_t* s_base) {
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t j = i * kBlock + threadIdx.x;
-        if (j < len) dst[gp[i]] = sx[j];
+        if (j < len) dst[slot_dest(s_dig, s_base, j)] = sx[j];
     }
 }
 
 // MODE 0: one segment [0, n).  MODE 1: the large segments of a bucketed group.  MODE 2: a
 // batch of tensors (each tensor is one segment; its parameters come from a device table).
-template <int R, typename CT, typename VT, int ITEMS, int MODE>
+// PK (MODE 0 only): 0 records as given; 1 pack the R coordinate arrays into one array of
+// 64-bit words on the way out; 2 unpack such words into R coordinate arrays.
+template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK>
 __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
+    static_assert(PK == 0 || MODE == 0, "packed records are a global-pass layout");
+    constexpr bool PACK = PK == 1, UNPACK = PK == 2;
     constexpr int TILE = kBlock * ITEMS;
     __shared__ uint64_t s_x[TILE];               // record exchange (4- or 8-byte words)
     __shared__ uint32_t s_cnt[kWaves * kBins];   // per-wave digit counters, then wave prefixes
@@ -415,19 +427,28 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
 
         // ---- key modes first: the tile's digit counts are published as early as possible;
         // the other arrays are loaded while the look-back waits on the predecessors
-        CT c[R][ITEMS];
+        CT c[UNPACK ? 1 : R][ITEMS];
+        uint64_t pw[UNPACK ? ITEMS : 1];  // packed words (unpacking pass)
         VT v[ITEMS];
         uint32_t dg[ITEMS], lp[ITEMS];
+        if constexpr (UNPACK) {
+            // the group's composite key sits in the low bits of every word
+            load_items<uint64_t, ITEMS>((const uint64_t*)src_crd[0], start, len, wb, pw);
 #pragma unroll
-        for (int m = 0; m < R; ++m)
-            if (m < r && key.mask[m]) load_items<CT, ITEMS>((const CT*)src_crd[m], start, len, wb, c[m]);
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            uint64_t kv = 0;
+            for (int i = 0; i < ITEMS; ++i) dg[i] = (uint32_t)(pw[i] >> lo_bit) & dmask;
+        } else {
 #pragma unroll
             for (int m = 0; m < R; ++m)
-                if (m < r && key.mask[m]) kv |= (((uint64_t)c[m][i] >> key.src_lo[m]) & key.mask[m]) << key.dst[m];
-            dg[i] = (uint32_t)(kv >> lo_bit) & dmask;
+                if (m < r && key.mask[m]) load_items<CT, ITEMS>((const CT*)src_crd[m], start, len, wb, c[m]);
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                uint64_t kv = 0;
+#pragma unroll
+                for (int m = 0; m < R; ++m)
+                    if (m < r && key.mask[m])
+                        kv |= (((uint64_t)c[m][i] >> key.src_lo[m]) & key.mask[m]) << key.dst[m];
+                dg[i] = (uint32_t)(kv >> lo_bit) & dmask;
+            }
         }
 
         // ---- stable rank inside each wave: ballot-match the digit, count lanes below
@@ -464,9 +485,11 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
             uint32_t* st = a.status + (size_t)t * kBins;
             st_status(&st[b], (first ? kFlagP : kFlagA) | tcnt);
             // the rest of the records, in flight during the scans and the look-back
+            if constexpr (!UNPACK) {
 #pragma unroll
-            for (int m = 0; m < R; ++m)
-                if (m < r && !key.mask[m]) load_items<CT, ITEMS>((const CT*)src_crd[m], start, len, wb, c[m]);
+                for (int m = 0; m < R; ++m)
+                    if (m < r && !key.mask[m]) load_items<CT, ITEMS>((const CT*)src_crd[m], start, len, wb, c[m]);
+            }
             load_items<VT, ITEMS>((const VT*)src_val, start, len, wb, v);
             const uint32_t tstart = block_excl_scan(tcnt, s_tmp, nullptr);
             const uint32_t hstart = block_excl_scan(hist[b], s_tmp + kWaves, nullptr);
@@ -491,25 +514,48 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
             }
         }
         __syncthreads();
-        uint32_t gp[ITEMS];
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t j = i * kBlock + tid;
-            gp[i] = (j < len) ? s_base[s_dig[j]] + j : 0;
-        }
 
         // ---- move every array through LDS: contiguous runs per digit on the way out
+        if constexpr (UNPACK) {
+            stage_items<uint64_t, ITEMS>(s_x, len, wb, pw, lp);
+            __syncthreads();
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
-            if (m >= r) break;
-            stage_items<CT, ITEMS>((CT*)s_x, len, wb, c[m], lp);
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t j = i * kBlock + tid;
+                if (j < len) {
+                    const uint64_t w = s_x[j];
+                    const uint32_t g = slot_dest(s_dig, s_base, j);
+#pragma unroll
+                    for (int m = 0; m < R; ++m)
+                        if (m < r) ((CT*)dst_crd[m])[g] = (CT)((w >> a.pk_pos[m]) & a.pk_mask[m]);
+                }
+            }
             __syncthreads();
-            drain_items<CT, ITEMS>((const CT*)s_x, (CT*)dst_crd[m], len, gp);
+        } else if constexpr (PACK) {
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                uint64_t w = 0;
+#pragma unroll
+                for (int m = 0; m < R; ++m)
+                    if (m < r) w |= ((uint64_t)c[m][i] & a.pk_mask[m]) << a.pk_pos[m];
+                if (wb + i * 64 < len) s_x[lp[i]] = w;
+            }
             __syncthreads();
+            drain_items<uint64_t, ITEMS>(s_x, (uint64_t*)dst_crd[0], len, s_dig, s_base);
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                if (m >= r) break;
+                stage_items<CT, ITEMS>((CT*)s_x, len, wb, c[m], lp);
+                __syncthreads();
+                drain_items<CT, ITEMS>((const CT*)s_x, (CT*)dst_crd[m], len, s_dig, s_base);
+                __syncthreads();
+            }
         }
         stage_items<VT, ITEMS>((VT*)s_x, len, wb, v, lp);
         __syncthreads();
-        drain_items<VT, ITEMS>((const VT*)s_x, (VT*)dst_val, len, gp);
+        drain_items<VT, ITEMS>((const VT*)s_x, (VT*)dst_val, len, s_dig, s_base);
         __syncthreads();
     }
 }
@@ -1267,9 +1313,9 @@ int resident_blocks(K kernel) {
     return per * device_cu_count();
 }
 
-template <int R, typename CT, typename VT, int ITEMS, int MODE>
+template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK = 0>
 hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
-    auto kern = k_digit<R, CT, VT, ITEMS, MODE>;
+    auto kern = k_digit<R, CT, VT, ITEMS, MODE, PK>;
     static int resident = 0;
     if (!resident) resident = resident_blocks(kern);
     const uint32_t grid = (uint32_t)std::max(1, std::min<int>((int)a.ntiles, resident));
@@ -1277,15 +1323,18 @@ hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int R, typename CT, typename VT, int ITEMS>
+hipError_t digit_ri(const DigitArgs& a, hipStream_t s) {
+    if (a.seg_mode == 2) return digit_rs<R, CT, VT, ITEMS, 2>(a, s);
+    if (a.seg_mode == 1) return digit_rs<R, CT, VT, ITEMS, 1>(a, s);
+    if (a.pk == 1) return digit_rs<R, CT, VT, ITEMS, 0, 1>(a, s);
+    if (a.pk == 2) return digit_rs<R, CT, VT, ITEMS, 0, 2>(a, s);
+    return digit_rs<R, CT, VT, ITEMS, 0>(a, s);
+}
+
 template <int R, typename CT, typename VT>
 hipError_t digit_r(const DigitArgs& a, int items, hipStream_t s) {
-    const int mode = a.seg_mode;
-    if (items == 16) {
-        if (mode == 2) return digit_rs<R, CT, VT, 16, 2>(a, s);
-        return mode ? digit_rs<R, CT, VT, 16, 1>(a, s) : digit_rs<R, CT, VT, 16, 0>(a, s);
-    }
-    if (mode == 2) return digit_rs<R, CT, VT, 8, 2>(a, s);
-    return mode ? digit_rs<R, CT, VT, 8, 1>(a, s) : digit_rs<R, CT, VT, 8, 0>(a, s);
+    return items == 16 ? digit_ri<R, CT, VT, 16>(a, s) : digit_ri<R, CT, VT, 8>(a, s);
 }
 
 }  // namespace
