@@ -27,6 +27,8 @@ constexpr uint32_t kFlagA = 1u << 30;  // aggregate of this tile only
 constexpr uint32_t kFlagP = 2u << 30;  // inclusive prefix up to this tile
 constexpr uint32_t kCntMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 20;
+// Word 3 of a raw (unformatted, unswizzled) buffer resource on gfx9-family targets.
+constexpr int kBufferWord3 = 0x00020000;
 constexpr int kWaves = kBlock / 64;
 
 __device__ __forceinline__ uint32_t ld_status(const uint32_t* p) {
@@ -314,11 +316,20 @@ __device__ __forceinline__ uint32_t look_back(const uint32_t* status, uint32_t t
 template <typename T, int ITEMS>
 __device__ __forceinline__ void load_items(const T* __restrict__ src, uint32_t start, uint32_t len,
                                            uint32_t wb, T (&x)[ITEMS]) {
-    const T* tile = src + start;  // uniform base; per-item offsets stay small
+    // A buffer resource over exactly this tile's records: one offset register per thread, the
+    // per-item offsets in scalar registers, and the hardware range check returns 0 past `len`.
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(src + start), 0, (int)(len * sizeof(T)), kBufferWord3);
+    const int voff = (int)(wb * sizeof(T));
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t off = wb + i * 64;
-        x[i] = off < len ? tile[off] : T(0);
+        const int soff = i * 64 * (int)sizeof(T);
+        if constexpr (sizeof(T) == 8) {
+            const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
+            x[i] = (T)(((uint64_t)w[1] << 32) | w[0]);
+        } else {
+            x[i] = (T)__builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0);
+        }
     }
 }
 
@@ -338,7 +349,7 @@ __device__ __forceinline__ uint32_t slot_dest(const uint8_t* s_dig, const uint32
 template <typename T, int ITEMS>
 __device__ __forceinline__ void drain_items(const T* sx, T* __restrict__ dst, uint32_t len, const uint8_t* s_dig,
                                             const uint32_t* s_base) {
-#pragma unroll
+#pragma unroll 4
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t j = i * kBlock + threadIdx.x;
         if (j < len) dst[slot_dest(s_dig, s_base, j)] = sx[j];
@@ -361,8 +372,10 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
     __shared__ uint8_t s_dig[TILE];
     __shared__ uint32_t s_tmp[2 * kWaves];
     __shared__ uint32_t s_geo[6];                // tile, start, len, segment base, k, first tile
+    __shared__ uint32_t s_hpre[kBins];           // one segment: exclusive prefix of the digit counts
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (MODE == 0) s_hpre[tid] = block_excl_scan(a.hist[tid], s_tmp, nullptr);  // same for every tile
 
     for (;;) {
         if (tid == 0) {
@@ -458,7 +471,9 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
             const bool ok = (wb + i * 64) < len;
             const uint32_t d = dg[i];
             uint64_t peers = ballot(ok);
-            for (int b = 0; b < nbits; ++b) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {  // digits have at most 8 bits
+                if (b >= nbits) break;
                 const bool bit = (d >> b) & 1u;
                 const uint64_t bb = ballot(bit);
                 peers &= bit ? bb : ~bb;
@@ -492,7 +507,7 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
             }
             load_items<VT, ITEMS>((const VT*)src_val, start, len, wb, v);
             const uint32_t tstart = block_excl_scan(tcnt, s_tmp, nullptr);
-            const uint32_t hstart = block_excl_scan(hist[b], s_tmp + kWaves, nullptr);
+            const uint32_t hstart = MODE == 0 ? s_hpre[b] : block_excl_scan(hist[b], s_tmp + kWaves, nullptr);
             uint32_t excl = 0;
             if (!first) {
                 excl = look_back(a.status, t, lowest, b, a.err);
