@@ -361,7 +361,7 @@ __device__ __forceinline__ void drain_items(const T* sx, T* __restrict__ dst, ui
 // PK (MODE 0 only): 0 records as given; 1 pack the R coordinate arrays into one array of
 // 64-bit words on the way out; 2 unpack such words into R coordinate arrays.
 template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK>
-__global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
+__device__ __forceinline__ void digit_body(const DigitArgs& a) {
     static_assert(PK == 0 || MODE == 0, "packed records are a global-pass layout");
     constexpr bool PACK = PK == 1, UNPACK = PK == 2;
     constexpr int TILE = kBlock * ITEMS;
@@ -573,6 +573,19 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
         drain_items<VT, ITEMS>((const VT*)s_x, (VT*)dst_val, len, s_dig, s_base);
         __syncthreads();
     }
+}
+
+template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK>
+__global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
+    digit_body<R, CT, VT, ITEMS, MODE, PK>(a);
+}
+
+// The same pass compiled for three resident workgroups per CU: for the record layouts whose
+// registers fit (packed words in, i.e. the middle and the unpacking passes), the extra
+// workgroup hides the look-back and barrier latencies of the other two.
+template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_digit3(DigitArgs a) {
+    digit_body<R, CT, VT, ITEMS, MODE, PK>(a);
 }
 
 // ------------------------------------------------------------------------------ buckets
@@ -1328,14 +1341,23 @@ int resident_blocks(K kernel) {
     return per * device_cu_count();
 }
 
-template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK = 0>
-hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
-    auto kern = k_digit<R, CT, VT, ITEMS, MODE, PK>;
-    static int resident = 0;
+// One resident grid of a persistent digit-pass kernel (`resident` caches its occupancy).
+template <typename K>
+hipError_t launch_persistent(K kern, int& resident, const DigitArgs& a, hipStream_t s) {
     if (!resident) resident = resident_blocks(kern);
     const uint32_t grid = (uint32_t)std::max(1, std::min<int>((int)a.ntiles, resident));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
+}
+
+template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK = 0>
+hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
+    static int resident = 0;
+    // packed words in (R = 1 with 64-bit words, or unpacking): three workgroups per CU
+    if constexpr (MODE == 0 && ITEMS == 16 && (PK == 2 || (R == 1 && sizeof(CT) == 8 && PK == 0)))
+        return launch_persistent(k_digit3<R, CT, VT, ITEMS, MODE, PK>, resident, a, s);
+    else
+        return launch_persistent(k_digit<R, CT, VT, ITEMS, MODE, PK>, resident, a, s);
 }
 
 template <int R, typename CT, typename VT, int ITEMS>
