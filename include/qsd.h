@@ -70,6 +70,12 @@ typedef enum qsd_sched_t {
 } qsd_sched_t;
 
 #define QSD_VALIDATE 1u   /* qsd_transpose checks ranges and input order first (synchronises) */
+/* Bucketed groups (PartialSort calls that keep a prefix, Alg. 2) always run as bucket
+ * discovery plus segment-local sorts.  Without this flag, a bucketed group whose nonzeros pack
+ * into one 64-bit word is run as one global sort on (prefix, keys) with packed records when
+ * that adds at most two digit passes: the same stable result (the input is sorted on the
+ * prefix), usually cheaper. */
+#define QSD_KEEP_BUCKETS 2u
 
 typedef struct qsd_desc {
     int32_t order;              /* r, 1..QSD_MAX_ORDER */
@@ -79,7 +85,7 @@ typedef struct qsd_desc {
     qsd_value_t val_type;
     const int32_t* in_order;    /* host, r entries, permutation of 0..r-1 (tau) */
     const int32_t* out_order;   /* host, r entries, permutation of 0..r-1 (sigma) */
-    uint32_t flags;             /* QSD_VALIDATE */
+    uint32_t flags;             /* QSD_VALIDATE | QSD_KEEP_BUCKETS */
 } qsd_desc;
 
 typedef struct qsd_plan_s* qsd_plan_t;

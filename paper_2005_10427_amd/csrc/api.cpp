@@ -184,6 +184,8 @@ qsd_status check_desc(const qsd_desc* d) {
 
 }  // namespace
 
+static_assert(QSD_KEEP_BUCKETS == kKeepBuckets, "plan flag values differ");
+
 // Argument check shared with the selector's entry points.
 namespace qsd {
 qsd_status desc_status(const qsd_desc* d) { return check_desc(d); }

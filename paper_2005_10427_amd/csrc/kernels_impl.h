@@ -29,6 +29,14 @@ constexpr uint32_t kCntMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 20;
 // Word 3 of a raw (unformatted, unswizzled) buffer resource on gfx9-family targets.
 constexpr int kBufferWord3 = 0x00020000;
+// Digit-pass schedule choices (compile-time tuning): issue every load of a tile before the
+// ranking, and rank with two interleaved counter chains per wave.
+#ifndef QSD_LOADS_UPFRONT
+#define QSD_LOADS_UPFRONT 0
+#endif
+#ifndef QSD_RANK2
+#define QSD_RANK2 1
+#endif
 constexpr int kWaves = kBlock / 64;
 
 __device__ __forceinline__ uint32_t ld_status(const uint32_t* p) {
@@ -367,6 +375,7 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
     constexpr int TILE = kBlock * ITEMS;
     __shared__ uint64_t s_x[TILE];               // record exchange (4- or 8-byte words)
     __shared__ uint32_t s_cnt[kWaves * kBins];   // per-wave digit counters, then wave prefixes
+    __shared__ uint32_t s_cnt2[QSD_RANK2 ? kWaves * kBins : 1];  // second half of each wave's items
     __shared__ uint32_t s_tstart[kBins];         // first local slot of each digit
     __shared__ uint32_t s_base[kBins];           // global slot of local slot 0 of each digit
     __shared__ uint8_t s_dig[TILE];
@@ -463,26 +472,51 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                 dg[i] = (uint32_t)(kv >> lo_bit) & dmask;
             }
         }
-
-        // ---- stable rank inside each wave: ballot-match the digit, count lanes below
-        for (int b = lane; b < kBins; b += 64) s_cnt[wave * kBins + b] = 0;
+        if constexpr (QSD_LOADS_UPFRONT) {  // every array in flight before the ranking
+            if constexpr (!UNPACK) {
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const bool ok = (wb + i * 64) < len;
-            const uint32_t d = dg[i];
-            uint64_t peers = ballot(ok);
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {  // digits have at most 8 bits
-                if (b >= nbits) break;
-                const bool bit = (d >> b) & 1u;
-                const uint64_t bb = ballot(bit);
-                peers &= bit ? bb : ~bb;
+                for (int m = 0; m < R; ++m)
+                    if (m < r && !key.mask[m]) load_items<CT, ITEMS>((const CT*)src_crd[m], start, len, wb, c[m]);
             }
-            const uint32_t below = lanes_below(peers);
-            uint32_t old = 0;
-            if (ok) old = s_cnt[wave * kBins + d];
-            lp[i] = old + below;
-            if (ok && below == 0) s_cnt[wave * kBins + d] = old + (uint32_t)__popcll(peers);
+            load_items<VT, ITEMS>((const VT*)src_val, start, len, wb, v);
+        }
+
+        // ---- stable rank inside each wave: ballot-match the digit, count lanes below.  With
+        // two counter sets, the first and second halves of a wave's items form two independent
+        // read-modify-write chains on LDS; the second half then adds the first half's totals.
+        for (int b = lane; b < kBins; b += 64) {
+            s_cnt[wave * kBins + b] = 0;
+            if constexpr (QSD_RANK2) s_cnt2[wave * kBins + b] = 0;
+        }
+        constexpr int kHalf = QSD_RANK2 ? ITEMS / 2 : ITEMS;
+#pragma unroll
+        for (int h = 0; h < kHalf; ++h) {
+#pragma unroll
+            for (int part = 0; part < (QSD_RANK2 ? 2 : 1); ++part) {
+                const int i = part * kHalf + h;
+                uint32_t* cnt = (QSD_RANK2 && part) ? s_cnt2 : s_cnt;
+                const bool ok = (wb + i * 64) < len;
+                const uint32_t d = dg[i];
+                uint64_t peers = ballot(ok);
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {  // digits have at most 8 bits
+                    if (b >= nbits) break;
+                    const bool bit = (d >> b) & 1u;
+                    const uint64_t bb = ballot(bit);
+                    peers &= bit ? bb : ~bb;
+                }
+                const uint32_t below = lanes_below(peers);
+                uint32_t old = 0;
+                if (ok) old = cnt[wave * kBins + d];
+                lp[i] = old + below;
+                if (ok && below == 0) cnt[wave * kBins + d] = old + (uint32_t)__popcll(peers);
+            }
+        }
+        if constexpr (QSD_RANK2) {
+#pragma unroll
+            for (int i = kHalf; i < ITEMS; ++i)
+                if ((wb + i * 64) < len) lp[i] += s_cnt[wave * kBins + dg[i]];
+            for (int b = lane; b < kBins; b += 64) s_cnt[wave * kBins + b] += s_cnt2[wave * kBins + b];
         }
         __syncthreads();
 
@@ -500,12 +534,15 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
             uint32_t* st = a.status + (size_t)t * kBins;
             st_status(&st[b], (first ? kFlagP : kFlagA) | tcnt);
             // the rest of the records, in flight during the scans and the look-back
-            if constexpr (!UNPACK) {
+            if constexpr (!QSD_LOADS_UPFRONT) {
+                if constexpr (!UNPACK) {
 #pragma unroll
-                for (int m = 0; m < R; ++m)
-                    if (m < r && !key.mask[m]) load_items<CT, ITEMS>((const CT*)src_crd[m], start, len, wb, c[m]);
+                    for (int m = 0; m < R; ++m)
+                        if (m < r && !key.mask[m])
+                            load_items<CT, ITEMS>((const CT*)src_crd[m], start, len, wb, c[m]);
+                }
+                load_items<VT, ITEMS>((const VT*)src_val, start, len, wb, v);
             }
-            load_items<VT, ITEMS>((const VT*)src_val, start, len, wb, v);
             const uint32_t tstart = block_excl_scan(tcnt, s_tmp, nullptr);
             const uint32_t hstart = MODE == 0 ? s_hpre[b] : block_excl_scan(hist[b], s_tmp + kWaves, nullptr);
             uint32_t excl = 0;

@@ -116,7 +116,20 @@ bool make_group(PlanData& p, RawGroup raw, std::vector<Group>* out) {
     // In-LDS segment sorts put a 12-bit segment number above the key in one 64-bit word.
     // Wider keys are sorted globally with the prefix as the most significant part instead:
     // the input is sorted on the prefix, so a stable sort on (prefix, keys) keeps buckets.
-    if (g.segmented && g.key_bits > 52) {
+    bool flatten = g.segmented && g.key_bits > 52;
+    if (g.segmented && !flatten && !(p.flags & kKeepBuckets)) {
+        // Bucket discovery plus segment sorts against one global sort on (prefix, keys) with
+        // packed records: prefer the latter when every nonzero packs into 64 bits and the
+        // prefix adds at most two digit passes (a cost rule in the spirit of Sec. 5).
+        int total = 0, prefix_bits = 0;
+        for (int m = 0; m < p.r; ++m) total += p.bits[m];
+        for (int m : g.prefix) prefix_bits += p.bits[m];
+        const int flat_bits = prefix_bits + g.key_bits;
+        const int d_key = (g.key_bits + p.radix_bits - 1) / p.radix_bits;
+        const int d_flat = (flat_bits + p.radix_bits - 1) / p.radix_bits;
+        flatten = total <= 64 && flat_bits <= 64 && d_flat <= d_key + 2;
+    }
+    if (flatten) {
         std::vector<int> flat;
         for (int m : g.prefix)
             if (p.bits[m] > 0) flat.push_back(m);

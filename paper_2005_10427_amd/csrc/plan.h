@@ -21,6 +21,7 @@
 namespace qsd {
 
 constexpr int kMaxR = 8;
+constexpr uint32_t kKeepBuckets = 2;  // plan flag: bucketed groups stay segment sorts
 constexpr int kMaxPassesPerSub = 16;
 
 // key64 = OR over modes m of ((crd[m] >> src_lo[m]) & ((1 << width[m]) - 1)) << dst[m]

@@ -16,6 +16,7 @@ QSD_I32, QSD_I64 = 0, 1
 QSD_F32, QSD_F64 = 0, 1
 SCHED = {"auto": 0, "minimal": 1, "top2": 2, "lsd": 3}
 QSD_VALIDATE = 1
+QSD_KEEP_BUCKETS = 2
 MAX_ORDER = 8
 
 

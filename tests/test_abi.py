@@ -51,9 +51,11 @@ def _parse(desc):
     return head, calls, groups
 
 
-def _plan(r, tau, sigma, sched, extents=None, nnz=1000):
+def _plan(r, tau, sigma, sched, extents=None, nnz=1000, flags=None):
+    """Plan structure; by default bucketed groups are kept as such (Alg. 3's grouping)."""
     extents = extents or [7] * r
-    h = qsd.qsd_plan(r, nnz, extents, qsd.QSD_I32, qsd.QSD_F64, tau, sigma, sched)
+    flags = qsd.QSD_KEEP_BUCKETS if flags is None else flags
+    h = qsd.qsd_plan(r, nnz, extents, qsd.QSD_I32, qsd.QSD_F64, tau, sigma, sched, flags)
     try:
         return _parse(qsd.qsd_plan_describe(h))
     finally:
@@ -101,6 +103,25 @@ def test_digit_split_covers_key_bits(lib):
     assert groups[0]["keys"] == "2,1" and int(groups[0]["bits"]) == 36 and int(groups[0]["passes"]) == 5
     head, calls, groups = _plan(3, (0, 1, 2), (0, 2, 1), "minimal", extents=[500000, 20000, 2000000])
     assert groups[0]["prefix"] == "0" and groups[0]["segmented"] == "1" and int(groups[0]["bits"]) == 21
+
+
+def test_bucketed_group_flattening_rule(lib):
+    ext = [500000, 20000, 2000000]  # 19/15/21 bits: every nonzero packs into 55 bits
+    # (0,2,1): bucket prefix 0 (19 bits) over key 2 (21 bits): 3 key passes, 5 flattened
+    _, calls, groups = _plan(3, (0, 1, 2), (0, 2, 1), "minimal", extents=ext, flags=0)
+    assert calls == [((0,), 2)]  # the PartialSort calls are Alg. 3's either way
+    assert groups == [dict(prefix="", keys="0,2", bits="40", passes="5", segmented="0")]
+    # a 4-mode case where the prefix would add three passes keeps its buckets
+    ext4 = [1000000, 100000, 1000, 50]  # 20/17/10/6 bits
+    _, _, groups = _plan(4, (0, 1, 2, 3), (0, 1, 3, 2), "minimal", extents=ext4, flags=0)
+    assert groups[0]["segmented"] == "1" and groups[0]["prefix"] == "0,1"
+    # a 4-mode case where it adds two: flattened
+    _, _, groups = _plan(4, (0, 1, 2, 3), (0, 2, 1, 3), "minimal", extents=ext4, flags=0)
+    assert groups[0]["segmented"] == "0" and groups[0]["keys"] == "0,2"
+    # too wide to pack (int32 extents summing past 64 bits): buckets kept
+    _, _, groups = _plan(4, (0, 1, 2, 3), (0, 2, 1, 3), "minimal", extents=[1 << 20, 1 << 20, 1 << 20, 1 << 10],
+                         flags=0)
+    assert groups[0]["segmented"] == "1"
 
 
 def test_extent_one_modes_need_no_pass(lib):

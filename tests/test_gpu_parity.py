@@ -26,10 +26,11 @@ def dev(T):
     return crd, val
 
 
-def gpu_transpose(qsd, T, sigma, sched="minimal", crd_val=None):
+def gpu_transpose(qsd, T, sigma, sched="minimal", crd_val=None, flags=0):
     import torch
     crd, val = crd_val if crd_val is not None else dev(T)
-    P = qsd.Plan(T.extents, T.in_order, sigma, max(T.nnz, 1), str(T.crd[0].dtype), str(T.val.dtype), sched)
+    P = qsd.Plan(T.extents, T.in_order, sigma, max(T.nnz, 1), str(T.crd[0].dtype), str(T.val.dtype), sched,
+                 flags)
     out_crd, out_val = P.transpose(crd, val)
     torch.cuda.synchronize()
     assert P.device_status() == 0
@@ -45,11 +46,14 @@ def assert_bits_equal(got, want):
     assert np.array_equal(g_val.view(u), w_val.view(u)), "values differ"
 
 
-def check(qsd, T, sigma, sched="minimal", crd_val=None):
-    note(f"r={T.order} n={T.nnz} ext={T.extents} tau={T.in_order} sigma={sigma} sched={sched}")
-    got = gpu_transpose(qsd, T, sigma, sched, crd_val)
+def check(qsd, T, sigma, sched="minimal", crd_val=None, flags=(0, 2)):
+    """Both ways of running bucketed groups: flattened where cheaper (0) and always as
+    segment sorts (QSD_KEEP_BUCKETS = 2)."""
     want = oracle_transpose(T.crd, T.val, sigma)
-    assert_bits_equal(got, want)
+    for fl in ((flags,) if isinstance(flags, int) else flags):
+        note(f"r={T.order} n={T.nnz} ext={T.extents} tau={T.in_order} sigma={sigma} sched={sched} flags={fl}")
+        got = gpu_transpose(qsd, T, sigma, sched, crd_val, fl)
+        assert_bits_equal(got, want)
 
 
 def test_small_config_full_size(gpu_lib):
