@@ -1091,6 +1091,9 @@ qsd_status qsd_batch_transpose(qsd_batch_t b, void* ws, size_t ws_bytes, hipStre
         ha.status_zero = S[0];
         const int grid = (int)std::max<uint32_t>(1, std::min<uint32_t>(b->total_tiles, (uint32_t)device_cu_count() * 4));
         QSD_CK(timed(kHistBatch, 0, stream, [&] { return launch_hist_batch(ha, b->rmax, b->crd_bytes, grid, stream); }));
+        QSD_CK(timed(kHistBatch, 0, stream, [&] {
+            return launch_hist_prefix((uint32_t*)(W + b->off_hist), (uint32_t)(b->hist_words / kBins), stream);
+        }));
     }
     if (!b->small.empty()) {
         const auto* jobs = (const BatchSmallJob*)(T + b->tab_sjob);

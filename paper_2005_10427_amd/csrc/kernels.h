@@ -54,7 +54,7 @@ struct BatchPass {
     int32_t lo, bits;
     int32_t r;
     uint32_t n;
-    const uint32_t* hist;       // 256 digit counts of this pass over the tensor
+    const uint32_t* hist;       // exclusive prefix of this pass's 256 digit counts over the tensor
     uint32_t tile0;             // first (stable) tile id of the tensor
     int32_t active;             // 0: the tensor has no pass in this launch
     uint32_t pad[2];
@@ -220,6 +220,8 @@ hipError_t launch_digit(const DigitArgs& a, int r, int crd_bytes, int val_bytes,
 hipError_t launch_digit_batch(const DigitArgs& a, int rmax, int crd_bytes, int val_bytes, int items,
                               hipStream_t s);
 hipError_t launch_hist_batch(const BatchHistArgs& a, int rmax, int crd_bytes, int grid, hipStream_t s);
+// counts -> exclusive prefix, in place, for `blocks` consecutive blocks of 256 words
+hipError_t launch_hist_prefix(uint32_t* hist, uint32_t blocks, hipStream_t s);
 hipError_t launch_small_batch(const BatchSmallJob* jobs, uint32_t njobs, int rmax, int crd_bytes,
                               int val_bytes, hipStream_t s);
 hipError_t launch_boundary(const BoundArgs& a, int crd_bytes, hipStream_t s);

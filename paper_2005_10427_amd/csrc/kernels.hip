@@ -147,6 +147,12 @@ hipError_t launch_hist_batch(const BatchHistArgs& a, int rmax, int crd_bytes, in
     return crd_bytes == 8 ? hist_batch_c<uint64_t>(a, rmax, grid, s) : hist_batch_c<uint32_t>(a, rmax, grid, s);
 }
 
+hipError_t launch_hist_prefix(uint32_t* hist, uint32_t blocks, hipStream_t s) {
+    if (!blocks) return hipSuccess;
+    hipLaunchKernelGGL(k_hist_prefix, dim3(blocks), dim3(kBlock), 0, s, hist);
+    return hipGetLastError();
+}
+
 template <typename CT, typename VT>
 hipError_t small_batch_cv(const BatchSmallJob* jobs, uint32_t njobs, int rmax, hipStream_t s) {
     const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(njobs, (uint32_t)device_cu_count() * 8));

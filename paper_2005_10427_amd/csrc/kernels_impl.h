@@ -544,7 +544,10 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                 load_items<VT, ITEMS>((const VT*)src_val, start, len, wb, v);
             }
             const uint32_t tstart = block_excl_scan(tcnt, s_tmp, nullptr);
-            const uint32_t hstart = MODE == 0 ? s_hpre[b] : block_excl_scan(hist[b], s_tmp + kWaves, nullptr);
+            // one segment: computed once per workgroup; batch: offsets stored by k_hist_prefix
+            const uint32_t hstart = MODE == 0   ? s_hpre[b]
+                                    : MODE == 2 ? hist[b]
+                                                : block_excl_scan(hist[b], s_tmp + kWaves, nullptr);
             uint32_t excl = 0;
             if (!first) {
                 excl = look_back(a.status, t, lowest, b, a.err);
@@ -969,80 +972,119 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
 // ------------------------------------------------------------------------------ batches
 
 // Upfront digit histograms of every pass of every tensor of a batch.  Each workgroup takes a
-// static range of stable tiles and flushes its counts whenever the tensor changes.  Also
-// clears the look-back words of the first batched launch.
+// static range of stable tiles; the tensor's key spec and pass list are held in registers
+// and reloaded only when the tensor changes, when the counts are flushed.  Also clears the
+// look-back words of the first batched launch.
 template <int R, typename CT>
 __global__ void __launch_bounds__(256) k_hist_batch(BatchHistArgs a) {
-    __shared__ uint32_t s_h[16 * kBins];
-    __shared__ uint32_t s_pp[16];  // lo | bits << 8 | sub << 16
+    constexpr int U = 8, MAXP = 16;
+    __shared__ uint32_t s_h[MAXP * kBins + kBins];  // + a spare block for items past the end
     const int tid = threadIdx.x, lane = tid & 63;
+    const uint32_t spare = MAXP * kBins;
+    for (int i = tid; i < MAXP * kBins; i += kBlock) s_h[i] = 0;
     const uint32_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;
     const uint32_t t0 = blockIdx.x * per, t1 = min(a.ntiles, t0 + per);
-    uint32_t cur = 0xFFFFFFFFu;
-    int words = 0;
+    uint32_t cur = 0xFFFFFFFFu, n = 0, tile0 = 0;
+    int npass = 0, nsub = 1, words = 0;
+    uint32_t* hist = nullptr;
+    uint32_t plo[MAXP], pmask[MAXP], psub[MAXP];
+    uint64_t km[2][R];
+    uint32_t ks[2][R], kd[2][R];
+    const CT* src[R];
+    auto flush = [&]() {
+        sync_after_lds_atomics();
+        for (int i = tid; i < words; i += kBlock) {
+            const uint32_t c = s_h[i];
+            if (c) atomicAdd(&hist[i], c);
+            s_h[i] = 0;
+        }
+    };
+    __syncthreads();
     for (uint32_t t = t0; t < t1; ++t) {
         const uint32_t j = a.tile_job[t];
         if (j != cur) {
-            sync_after_lds_atomics();
-            if (cur != 0xFFFFFFFFu) {
-                uint32_t* h = a.jobs[cur].hist;
-                for (int i = tid; i < words; i += kBlock) {
-                    const uint32_t c = s_h[i];
-                    if (c) atomicAdd(&h[i], c);
-                }
-            }
+            if (cur != 0xFFFFFFFFu) flush();
             cur = j;
-            words = a.jobs[j].npass * kBins;
-            for (int i = tid; i < words; i += kBlock) s_h[i] = 0;
-            if (tid < a.jobs[j].npass)
-                s_pp[tid] = (uint32_t)a.jobs[j].lo[tid] | ((uint32_t)a.jobs[j].bits[tid] << 8) |
-                            ((uint32_t)a.jobs[j].sub[tid] << 16);
+            const BatchHistJob& J = a.jobs[j];
+            npass = J.npass;
+            nsub = J.nsub;
+            n = J.n;
+            tile0 = J.tile0;
+            hist = J.hist;
+            words = npass * kBins;
+            const int r = J.r;
+#pragma unroll
+            for (int p = 0; p < MAXP; ++p) {
+                plo[p] = p < npass ? (uint32_t)J.lo[p] : 0u;
+                pmask[p] = p < npass ? (1u << J.bits[p]) - 1u : 0u;
+                psub[p] = p < npass ? (uint32_t)J.sub[p] : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int m = 0; m < R; ++m) {
+                    const bool on = q < nsub && m < r;
+                    km[q][m] = on ? J.key[q].mask[m] : 0ull;
+                    ks[q][m] = on ? (uint32_t)J.key[q].src_lo[m] : 0u;
+                    kd[q][m] = on ? (uint32_t)J.key[q].dst[m] : 0u;
+                }
+#pragma unroll
+            for (int m = 0; m < R; ++m) src[m] = (const CT*)J.crd[m];
             __syncthreads();
         }
-        const BatchHistJob& J = a.jobs[j];
-        const int r = J.r, nsub = J.nsub, npass = J.npass;
-        const uint32_t start = (t - J.tile0) * a.tile;
-        const uint32_t end = min(J.n, start + a.tile);
-        for (uint32_t base = start; base < end; base += kBlock) {
-            const uint32_t e = base + tid;
-            const bool ok = e < end;
-            CT c[R];
+        const uint32_t start = (t - tile0) * a.tile;
+        const uint32_t end = min(n, start + a.tile);
+        for (uint32_t base = start; base < end; base += kBlock * U) {
+            uint64_t k0[U], k1[U];
 #pragma unroll
-            for (int m = 0; m < R; ++m) c[m] = (m < r && ok) ? ((const CT*)J.crd[m])[e] : CT(0);
-            uint64_t kv[2] = {0, 0};
+            for (int u = 0; u < U; ++u) k0[u] = k1[u] = 0;
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                if (q >= nsub) break;
+            for (int m = 0; m < R; ++m) {
+                if (!(km[0][m] | km[1][m])) continue;
+                CT c[U];
 #pragma unroll
-                for (int m = 0; m < R; ++m)
-                    if (m < r && J.key[q].mask[m])
-                        kv[q] |= (((uint64_t)c[m] >> J.key[q].src_lo[m]) & J.key[q].mask[m]) << J.key[q].dst[m];
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t e = base + u * kBlock + tid;
+                    c[u] = e < end ? src[m][e] : CT(0);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    k0[u] |= (((uint64_t)c[u] >> ks[0][m]) & km[0][m]) << kd[0][m];
+                    k1[u] |= (((uint64_t)c[u] >> ks[1][m]) & km[1][m]) << kd[1][m];
+                }
             }
-            for (int p = 0; p < npass; ++p) {
-                const uint32_t pp = __builtin_amdgcn_readfirstlane(s_pp[p]);
-                const uint64_t k = (pp >> 16) ? kv[1] : kv[0];
-                const uint32_t slot = ok ? p * kBins + ((uint32_t)(k >> (pp & 0xFF)) & ((1u << ((pp >> 8) & 0xFF)) - 1u))
-                                         : 0xFFFFFFFFu;
-                const uint32_t prev = __shfl_up(slot, 1, 64);
-                const bool head = ok && ((lane == 0) || (prev != slot));
-                const uint64_t heads = ballot(head || !ok);
-                if (head) {
-                    const uint64_t after = (lane == 63) ? 0ull : (heads >> (lane + 1));
-                    const uint32_t run = after ? (uint32_t)__builtin_ctzll(after) + 1u : 64u - lane;
-                    atomicAdd(&s_h[slot], run);
+#pragma unroll
+            for (int p = 0; p < MAXP; ++p) {
+                if (p >= npass) break;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t e = base + u * kBlock + tid;
+                    const uint64_t key = psub[p] ? k1[u] : k0[u];
+                    const uint32_t slot = e < end ? p * kBins + ((uint32_t)(key >> plo[p]) & pmask[p]) : spare;
+                    // runs of one digit in consecutive lanes are added once, from their first lane
+                    const uint32_t prev = __shfl_up(slot, 1, 64);
+                    const bool head = (lane == 0) || (prev != slot);
+                    const uint64_t heads = ballot(head);
+                    if (head) {
+                        const uint64_t after = (lane == 63) ? 0ull : (heads >> (lane + 1));
+                        const uint32_t run = after ? (uint32_t)__builtin_ctzll(after) + 1u : 64u - lane;
+                        atomicAdd(&s_h[slot], run);
+                    }
                 }
             }
         }
         a.status_zero[(size_t)t * kBins + tid] = 0;
     }
-    sync_after_lds_atomics();
-    if (cur != 0xFFFFFFFFu) {
-        uint32_t* h = a.jobs[cur].hist;
-        for (int i = tid; i < words; i += kBlock) {
-            const uint32_t c = s_h[i];
-            if (c) atomicAdd(&h[i], c);
-        }
-    }
+    if (cur != 0xFFFFFFFFu) flush();
+}
+
+// Exclusive prefix of every 256-word block of digit counts, in place (one block per
+// workgroup): the digit passes of a batch then read their digit offsets directly.
+__global__ void __launch_bounds__(256) k_hist_prefix(uint32_t* hist) {
+    __shared__ uint32_t s_tmp[kWaves];
+    uint32_t* h = hist + (size_t)blockIdx.x * kBins;
+    const uint32_t c = h[threadIdx.x];
+    h[threadIdx.x] = block_excl_scan(c, s_tmp, nullptr);
 }
 
 // One small tensor per workgroup, sorted entirely in LDS by its flattened key: LSD passes
