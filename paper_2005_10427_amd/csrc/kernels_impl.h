@@ -37,6 +37,14 @@ constexpr int kBufferWord3 = 0x00020000;
 #ifndef QSD_RANK2
 #define QSD_RANK2 1
 #endif
+// Run the look-back after the tile-local work that does not need its result.
+#ifndef QSD_LATE_LOOKBACK
+#define QSD_LATE_LOOKBACK 0
+#endif
+// The packing pass also at three workgroups per CU (a few registers spill).
+#ifndef QSD_PACK3
+#define QSD_PACK3 0
+#endif
 constexpr int kWaves = kBlock / 64;
 
 __device__ __forceinline__ uint32_t ld_status(const uint32_t* p) {
@@ -520,7 +528,10 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
         }
         __syncthreads();
 
-        // ---- per digit: wave prefixes, tile count, look-back for the global offset
+        // ---- per digit: wave prefixes, tile count and the tile-local digit starts; the tile's
+        // counts are published at once
+        constexpr bool kEarly = QSD_LATE_LOOKBACK && (UNPACK || (!PACK && R == 1));
+        uint32_t tcnt, tstart, hstart;  // of digit b = tid
         {
             const uint32_t b = tid;
             uint32_t run = 0;
@@ -530,9 +541,8 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                 s_cnt[w * kBins + b] = run;
                 run += x;
             }
-            const uint32_t tcnt = run;
-            uint32_t* st = a.status + (size_t)t * kBins;
-            st_status(&st[b], (first ? kFlagP : kFlagA) | tcnt);
+            tcnt = run;
+            st_status(&a.status[(size_t)t * kBins + b], (first ? kFlagP : kFlagA) | tcnt);
             // the rest of the records, in flight during the scans and the look-back
             if constexpr (!QSD_LOADS_UPFRONT) {
                 if constexpr (!UNPACK) {
@@ -543,37 +553,74 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                 }
                 load_items<VT, ITEMS>((const VT*)src_val, start, len, wb, v);
             }
-            const uint32_t tstart = block_excl_scan(tcnt, s_tmp, nullptr);
+            tstart = block_excl_scan(tcnt, s_tmp, nullptr);
             // one segment: computed once per workgroup; batch: offsets stored by k_hist_prefix
-            const uint32_t hstart = MODE == 0   ? s_hpre[b]
-                                    : MODE == 2 ? hist[b]
-                                                : block_excl_scan(hist[b], s_tmp + kWaves, nullptr);
+            hstart = MODE == 0   ? s_hpre[b]
+                     : MODE == 2 ? hist[b]
+                                 : block_excl_scan(hist[b], s_tmp + kWaves, nullptr);
+            s_tstart[b] = tstart;
+        }
+        // ---- the global offset of every digit: decoupled look-back over the predecessors
+        auto global_offsets = [&]() {
+            const uint32_t b = tid;
             uint32_t excl = 0;
             if (!first) {
                 excl = look_back(a.status, t, lowest, b, a.err);
-                st_status(&st[b], kFlagP | (excl + tcnt));
+                st_status(&a.status[(size_t)t * kBins + b], kFlagP | (excl + tcnt));
             }
-            s_tstart[b] = tstart;
             s_base[b] = seg_base + hstart + excl - tstart;
             if (a.status_next) a.status_next[(size_t)t * kBins + b] = 0;
-        }
+        };
+        if constexpr (!QSD_LATE_LOOKBACK) global_offsets();
         __syncthreads();
 
-        // ---- local slot of every record, then the digit of every local slot
+        // ---- local slot of every record and the digit of every local slot; the first array is
+        // staged in LDS by local slot in the same sweep when it is already in registers.  None of
+        // this needs the global offsets, so the look-back runs after it, giving the predecessors
+        // time to publish their prefixes.
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             if ((wb + i * 64) < len) {
                 const uint32_t d = dg[i];
                 lp[i] += s_tstart[d] + s_cnt[wave * kBins + d];
                 s_dig[lp[i]] = (uint8_t)d;
+                if constexpr (!QSD_LATE_LOOKBACK || kEarly) {
+                    if constexpr (UNPACK) {
+                        s_x[lp[i]] = pw[i];
+                    } else if constexpr (PACK) {
+                        uint64_t w = 0;
+#pragma unroll
+                        for (int m = 0; m < R; ++m)
+                            if (m < r) w |= ((uint64_t)c[m][i] & a.pk_mask[m]) << a.pk_pos[m];
+                        s_x[lp[i]] = w;
+                    } else {
+                        ((CT*)s_x)[lp[i]] = c[0][i];
+                    }
+                }
             }
         }
+        if constexpr (QSD_LATE_LOOKBACK) global_offsets();
         __syncthreads();
+        if constexpr (QSD_LATE_LOOKBACK && !kEarly) {  // first array staged now that it has arrived
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                if ((wb + i * 64) < len) {
+                    if constexpr (PACK) {
+                        uint64_t w = 0;
+#pragma unroll
+                        for (int m = 0; m < R; ++m)
+                            if (m < r) w |= ((uint64_t)c[m][i] & a.pk_mask[m]) << a.pk_pos[m];
+                        s_x[lp[i]] = w;
+                    } else {
+                        ((CT*)s_x)[lp[i]] = c[0][i];
+                    }
+                }
+            }
+            __syncthreads();
+        }
 
         // ---- move every array through LDS: contiguous runs per digit on the way out
         if constexpr (UNPACK) {
-            stage_items<uint64_t, ITEMS>(s_x, len, wb, pw, lp);
-            __syncthreads();
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
                 const uint32_t j = i * kBlock + tid;
@@ -587,23 +634,16 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
             }
             __syncthreads();
         } else if constexpr (PACK) {
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                uint64_t w = 0;
-#pragma unroll
-                for (int m = 0; m < R; ++m)
-                    if (m < r) w |= ((uint64_t)c[m][i] & a.pk_mask[m]) << a.pk_pos[m];
-                if (wb + i * 64 < len) s_x[lp[i]] = w;
-            }
-            __syncthreads();
             drain_items<uint64_t, ITEMS>(s_x, (uint64_t*)dst_crd[0], len, s_dig, s_base);
             __syncthreads();
         } else {
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 if (m >= r) break;
-                stage_items<CT, ITEMS>((CT*)s_x, len, wb, c[m], lp);
-                __syncthreads();
+                if (m > 0) {
+                    stage_items<CT, ITEMS>((CT*)s_x, len, wb, c[m], lp);
+                    __syncthreads();
+                }
                 drain_items<CT, ITEMS>((const CT*)s_x, (CT*)dst_crd[m], len, s_dig, s_base);
                 __syncthreads();
             }
@@ -1432,8 +1472,9 @@ hipError_t launch_persistent(K kern, int& resident, const DigitArgs& a, hipStrea
 template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK = 0>
 hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
     static int resident = 0;
-    // packed words in (R = 1 with 64-bit words, or unpacking): three workgroups per CU
-    if constexpr (MODE == 0 && ITEMS == 16 && (PK == 2 || (R == 1 && sizeof(CT) == 8 && PK == 0)))
+    // packed words in (R = 1 with 64-bit words, or unpacking) and the packing pass: three
+    // workgroups per CU
+    if constexpr (MODE == 0 && ITEMS == 16 && ((PK == 1 && QSD_PACK3) || PK == 2 || (R == 1 && sizeof(CT) == 8)))
         return launch_persistent(k_digit3<R, CT, VT, ITEMS, MODE, PK>, resident, a, s);
     else
         return launch_persistent(k_digit<R, CT, VT, ITEMS, MODE, PK>, resident, a, s);
