@@ -174,7 +174,8 @@ qsd_status qsd_batch_bind(qsd_batch_t batch, const qsd_batch_io* io, void* ws, s
 qsd_status qsd_batch_transpose(qsd_batch_t batch, void* ws, size_t ws_bytes, hipStream_t stream);
 /* Autotuner: tries items {8, 16} x radix bits {6, 7, 8} x small_cap {0, 1024, 4096}, `reps`
  * timed runs each (best of), on the bound buffers; applies and returns the fastest setting and
- * its time.  ws must be large enough for every candidate (qsd_batch_workspace_max). */
+ * its time.  qsd_batch_workspace_max: bytes enough for every tuning qsd_batch_set_tuning
+ * accepts (hence for every candidate of the autotuner). */
 qsd_status qsd_batch_workspace_max(qsd_batch_t batch, size_t* bytes);
 qsd_status qsd_batch_tune(qsd_batch_t batch, const qsd_batch_io* io, void* ws, size_t ws_bytes,
                           hipStream_t stream, int32_t reps, qsd_tuning* best, float* best_ms);

@@ -68,19 +68,23 @@ bool packable(const qsd_plan_s* q, const Group& g) {
     return true;
 }
 
-void pack_spec(const PlanData& p, const KeySpec& k, DigitArgs& da) {
+// Word layout of packed records: key modes at their place in the composite key (low bits),
+// the other modes above it.
+void pack_layout(int r, const int* bits, const KeySpec& k, int32_t* pos, uint64_t* mask) {
     int at = k.bits;
-    for (int m = 0; m < p.r; ++m) {
-        const int b = p.bits[m];
-        da.pk_mask[m] = b ? ((b >= 64) ? ~0ull : ((1ull << b) - 1)) : 0;
+    for (int m = 0; m < r; ++m) {
+        const int b = bits[m];
+        mask[m] = b ? ((b >= 64) ? ~0ull : ((1ull << b) - 1)) : 0;
         if (k.width[m]) {
-            da.pk_pos[m] = k.dst[m];
+            pos[m] = k.dst[m];
         } else {
-            da.pk_pos[m] = b ? at : 0;
+            pos[m] = b ? at : 0;
             at += b;
         }
     }
 }
+
+void pack_spec(const PlanData& p, const KeySpec& k, DigitArgs& da) { pack_layout(p.r, p.bits, k, da.pk_pos, da.pk_mask); }
 
 void make_layout(qsd_plan_s* q) {
     const PlanData& p = q->p;
@@ -752,10 +756,21 @@ struct BTensor {
     std::vector<SubKey> subs;    // least significant first
     int D = 0;                   // digit passes
     bool small = false;
+    bool packed = false;         // first pass packs, middle passes move words, last unpacks
     uint32_t tile0 = 0, tiles = 0;
     size_t rec_off = 0;          // workspace record area (large tensors)
+    size_t val_off = 0;          // workspace value array (large tensors)
+    size_t pk_off[2] = {0, 0};   // packed-word ping-pong buffers (packed tensors)
     size_t hist_word = 0;        // first histogram word (large tensors)
 };
+
+// Record layouts of a batched pass; every tensor's pass p has one, and each layout present
+// in pass p is one launch.
+enum BatchKind { kKindSoA = 0, kKindPack = 1, kKindWords = 2, kKindUnpack = 3, kKinds = 4 };
+int kind_of(const BTensor& x, int p) {
+    if (!x.packed) return kKindSoA;
+    return p == 0 ? kKindPack : (p == x.D - 1 ? kKindUnpack : kKindWords);
+}
 
 }  // namespace
 
@@ -765,14 +780,15 @@ struct qsd_batch_s {
     std::vector<BTensor> t;
     // derived from the tuning
     int items = 16, tile = 4096, maxD = 0;
+    bool pack = true;                              // packed records for tensors that fit
     uint32_t total_tiles = 0;
     std::vector<int> large, small;                 // tensor indices
-    std::vector<std::vector<uint32_t>> launch_tiles;  // per launch: stable tile ids
+    std::vector<std::vector<uint32_t>> launch_tiles;  // per (pass, layout): stable tile ids
     size_t hist_words = 0;
     // workspace layout
     size_t off_ctl = 0, off_rec = 0, off_hist = 0, off_status[2] = {0, 0}, off_tab = 0, total = 0;
     size_t tab_pass = 0, tab_map = 0, tab_job = 0, tab_hjob = 0, tab_sjob = 0, tab_bytes = 0;
-    std::vector<size_t> map_off;                   // per launch, word offset in the map table
+    std::vector<size_t> map_off;                   // per (pass, layout): word offset in the map table
     // bound host tables
     std::vector<char> host_tab;
     bool bound = false;
@@ -822,15 +838,29 @@ qsd_status batch_derive(qsd_batch_s* b) {
         b->total_tiles += x.tiles;
         x.hist_word = b->hist_words;
         b->hist_words += (size_t)x.D * kBins;
+        int total_bits = 0;
+        for (int m = 0; m < x.r; ++m) total_bits += x.bits[m];
+        x.packed = b->pack && x.D >= 2 && x.subs.size() == 1 && total_bits <= 64;
         x.rec_off = rec;
-        for (int m = 0; m <= x.r; ++m) rec = up(rec + (size_t)x.n * (m < x.r ? b->crd_bytes : b->val_bytes));
+        if (x.packed) {  // the coordinate arrays live only as words between the first and last pass
+            for (int k = 0; k < 2; ++k) {
+                x.pk_off[k] = rec;
+                rec = up(rec + (size_t)x.n * 8);
+            }
+        } else {
+            for (int m = 0; m < x.r; ++m) rec = up(rec + (size_t)x.n * b->crd_bytes);
+        }
+        x.val_off = rec;
+        rec = up(rec + (size_t)x.n * b->val_bytes);
         b->maxD = std::max(b->maxD, x.D);
     }
-    b->launch_tiles.assign(b->maxD, {});
+    b->launch_tiles.assign((size_t)b->maxD * kKinds, {});
     for (int p = 0; p < b->maxD; ++p)
         for (int i : b->large)
-            if (p < b->t[i].D)
-                for (uint32_t k = 0; k < b->t[i].tiles; ++k) b->launch_tiles[p].push_back(b->t[i].tile0 + k);
+            if (p < b->t[i].D) {
+                auto& lt = b->launch_tiles[(size_t)p * kKinds + kind_of(b->t[i], p)];
+                for (uint32_t k = 0; k < b->t[i].tiles; ++k) lt.push_back(b->t[i].tile0 + k);
+            }
     // layout
     size_t at = 0;
     b->off_ctl = at;
@@ -849,11 +879,11 @@ qsd_status batch_derive(qsd_batch_s* b) {
     b->tab_pass = tb;
     tb = up(tb + (size_t)b->maxD * nl * sizeof(BatchPass));
     b->tab_map = tb;
-    b->map_off.assign(b->maxD, 0);
+    b->map_off.assign(b->launch_tiles.size(), 0);
     size_t words = 0;
-    for (int p = 0; p < b->maxD; ++p) {
-        b->map_off[p] = words;
-        words += b->launch_tiles[p].size();
+    for (size_t l = 0; l < b->launch_tiles.size(); ++l) {
+        b->map_off[l] = words;
+        words += b->launch_tiles[l].size();
     }
     tb = up(tb + words * 4);
     b->tab_job = tb;
@@ -892,6 +922,8 @@ qsd_status qsd_batch_plan(const qsd_desc* descs, int32_t count, qsd_batch_t* out
             delete b;
             return QSD_ERR_UNSUPPORTED;
         }
+        if (i == 0)
+            if (const char* e = std::getenv("QSD_PACK")) b->pack = std::atoi(e) != 0;  // tuning override
         BTensor x;
         x.r = descs[i].order;
         x.n = (uint32_t)descs[i].nnz;
@@ -945,11 +977,13 @@ qsd_status qsd_batch_workspace(qsd_batch_t b, size_t* bytes) {
 
 qsd_status qsd_batch_workspace_max(qsd_batch_t b, size_t* bytes) {
     if (!b || !bytes) return QSD_ERR_NULL;
+    // every tuning qsd_batch_set_tuning accepts; small_cap = 0 makes every tensor large, which
+    // needs the most workspace for a given digit width and item count
     const qsd_tuning keep = b->tun;
     size_t mx = 0;
     for (int items : {8, 16})
-        for (int rb : {6, 7, 8})
-            for (int cap : {0, 1024, kSmallCap}) {
+        for (int rb = 4; rb <= 8; ++rb)
+            for (int cap : {0, keep.small_cap}) {
                 b->tun = qsd_tuning{items, rb, cap};
                 if (batch_derive(b) == QSD_OK) mx = std::max(mx, b->total);
             }
@@ -982,6 +1016,7 @@ qsd_status qsd_batch_bind(qsd_batch_t b, const qsd_batch_io* io, void* ws, size_
             auto buf = [&](int hop, int m) -> void* {
                 const bool to_out = ((x.D - 1 - hop) % 2) == 0;
                 if (to_out) return m < x.r ? q.out_crd[m] : q.out_val;
+                if (m == x.r) return W + b->off_rec + x.val_off;
                 size_t off = x.rec_off;
                 for (int k = 0; k < m; ++k) off = up(off + (size_t)x.n * b->crd_bytes);
                 return W + b->off_rec + off;
@@ -1003,9 +1038,31 @@ qsd_status qsd_batch_bind(qsd_batch_t b, const qsd_batch_io* io, void* ws, size_
             e.lo = x.subs[sub].passes[k].lo;
             e.bits = x.subs[sub].passes[k].bits;
             e.hist = (const uint32_t*)(W + b->off_hist) + x.hist_word + (size_t)p * kBins;
+            if (x.packed) {  // words in the tensor's two word buffers between the first and last pass
+                pack_layout(x.r, x.bits, x.subs[0].key, e.pk_pos, e.pk_mask);
+                void* P[2] = {W + b->off_rec + x.pk_off[0], W + b->off_rec + x.pk_off[1]};
+                const int kind = kind_of(x, p);
+                if (kind == kKindPack) {
+                    e.dst_crd[0] = P[0];
+                } else if (kind == kKindWords) {
+                    std::memset(e.src_crd, 0, sizeof(e.src_crd));
+                    std::memset(e.dst_crd, 0, sizeof(e.dst_crd));
+                    e.src_crd[0] = P[(p - 1) % 2];
+                    e.dst_crd[0] = P[p % 2];
+                    std::memset(&e.key, 0, sizeof(e.key));
+                    e.key.mask[0] = x.subs[0].key.bits >= 64 ? ~0ull : ((1ull << x.subs[0].key.bits) - 1);
+                    e.r = 1;
+                } else {  // unpacking: words in, coordinate arrays out
+                    std::memset(e.src_crd, 0, sizeof(e.src_crd));
+                    e.src_crd[0] = P[(p - 1) % 2];
+                }
+            }
         }
-        uint32_t* map = (uint32_t*)(H + b->tab_map) + b->map_off[p];
-        std::copy(b->launch_tiles[p].begin(), b->launch_tiles[p].end(), map);
+        for (int kind = 0; kind < kKinds; ++kind) {
+            const size_t l = (size_t)p * kKinds + kind;
+            uint32_t* map = (uint32_t*)(H + b->tab_map) + b->map_off[l];
+            std::copy(b->launch_tiles[l].begin(), b->launch_tiles[l].end(), map);
+        }
     }
     uint32_t* tj = (uint32_t*)(H + b->tab_job);
     BatchHistJob* hj = (BatchHistJob*)(H + b->tab_hjob);
@@ -1103,21 +1160,33 @@ qsd_status qsd_batch_transpose(qsd_batch_t b, void* ws, size_t ws_bytes, hipStre
     }
     const size_t nl = b->large.size();
     for (int p = 0; p < b->maxD; ++p) {
-        DigitArgs da{};
-        da.seg_mode = 2;
-        da.ntiles = (uint32_t)b->launch_tiles[p].size();
-        da.tile_map = (const uint32_t*)(T + b->tab_map) + b->map_off[p];
-        da.tile_job = (const uint32_t*)(T + b->tab_job);
-        da.batch = (const BatchPass*)(T + b->tab_pass) + (size_t)p * nl;
-        da.status = S[p % 2];
-        da.status_next = (p + 1 < b->maxD) ? S[(p + 1) % 2] : nullptr;
-        da.tile_counter = ctl + kCtlPassCnt + p;
-        da.err = ctl + kCtlErr;
-        double bytes = 0;
-        for (int i : b->large)
-            if (p < b->t[i].D) bytes += 2.0 * b->t[i].n * rec_bytes(b, b->t[i].r);
-        QSD_CK(timed(kDigitBatch, bytes, stream,
-                     [&] { return launch_digit_batch(da, b->rmax, b->crd_bytes, b->val_bytes, b->items, stream); }));
+        for (int kind = 0; kind < kKinds; ++kind) {
+            const size_t l = (size_t)p * kKinds + kind;
+            if (b->launch_tiles[l].empty()) continue;
+            DigitArgs da{};
+            da.seg_mode = 2;
+            da.pk = kind == kKindPack ? 1 : (kind == kKindUnpack ? 2 : 0);
+            da.ntiles = (uint32_t)b->launch_tiles[l].size();
+            da.tile_map = (const uint32_t*)(T + b->tab_map) + b->map_off[l];
+            da.tile_job = (const uint32_t*)(T + b->tab_job);
+            da.batch = (const BatchPass*)(T + b->tab_pass) + (size_t)p * nl;
+            da.status = S[p % 2];
+            da.status_next = (p + 1 < b->maxD) ? S[(p + 1) % 2] : nullptr;
+            da.tile_counter = ctl + kCtlPassCnt + l;
+            da.err = ctl + kCtlErr;
+            const int r_launch = kind == kKindWords ? 1 : b->rmax;
+            const int cb_launch = kind == kKindWords ? 8 : b->crd_bytes;
+            double bytes = 0;
+            for (int i : b->large) {
+                const BTensor& x = b->t[i];
+                if (p >= x.D || kind_of(x, p) != kind) continue;
+                const double soa = (double)rec_bytes(b, x.r), words = 8.0 + b->val_bytes;
+                bytes += x.n * (kind == kKindSoA ? 2 * soa : kind == kKindWords ? 2 * words : soa + words);
+            }
+            QSD_CK(timed(kDigitBatch, bytes, stream, [&] {
+                return launch_digit_batch(da, r_launch, cb_launch, b->val_bytes, b->items, stream);
+            }));
+        }
     }
 #undef QSD_CK
     return QSD_OK;

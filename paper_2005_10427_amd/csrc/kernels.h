@@ -58,6 +58,9 @@ struct BatchPass {
     uint32_t tile0;             // first (stable) tile id of the tensor
     int32_t active;             // 0: the tensor has no pass in this launch
     uint32_t pad[2];
+    // packed records: the layout of the 64-bit words (as DigitArgs::pk_pos / pk_mask)
+    int32_t pk_pos[8];
+    uint64_t pk_mask[8];
 };
 
 struct DigitArgs {
@@ -82,10 +85,11 @@ struct DigitArgs {
     const uint32_t* tile_job;   // batch mode: tensor (table entry) of every stable tile
     const BatchPass* batch;     // batch mode: this launch's table
     uint32_t* err;
-    // Packed records (global mode only).  pk = 1: read the r coordinate arrays, write one
+    // Packed records (global and batch modes).  pk = 1: read the r coordinate arrays, write one
     // array of 64-bit words sum_m (crd_m & pk_mask[m]) << pk_pos[m] (dst_crd[0]); pk = 2:
     // read such words (src_crd[0]; the digit is taken from the word directly) and write the r
-    // coordinate arrays back.  pk = 0: records as given.
+    // coordinate arrays back.  pk = 0: records as given.  In batch mode pk is the record layout
+    // of every tensor in the launch and the word layout comes from each tensor's table entry.
     int32_t pk;
     int32_t pk_pos[8];
     uint64_t pk_mask[8];

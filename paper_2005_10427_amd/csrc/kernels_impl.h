@@ -378,7 +378,7 @@ __device__ __forceinline__ void drain_items(const T* sx, T* __restrict__ dst, ui
 // 64-bit words on the way out; 2 unpack such words into R coordinate arrays.
 template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK>
 __device__ __forceinline__ void digit_body(const DigitArgs& a) {
-    static_assert(PK == 0 || MODE == 0, "packed records are a global-pass layout");
+    static_assert(PK == 0 || MODE != 1, "packed records are a global or batch layout");
     constexpr bool PACK = PK == 1, UNPACK = PK == 2;
     constexpr int TILE = kBlock * ITEMS;
     __shared__ uint64_t s_x[TILE];               // record exchange (4- or 8-byte words)
@@ -452,6 +452,8 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
         const void* src_val = MODE == 2 ? J->src_val : a.src_val;
         void* dst_val = MODE == 2 ? J->dst_val : a.dst_val;
         const uint32_t* hist = MODE == 2 ? J->hist : a.hist + (size_t)k * a.hist_stride;
+        const int32_t* pk_pos = MODE == 2 ? J->pk_pos : a.pk_pos;
+        const uint64_t* pk_mask = MODE == 2 ? J->pk_mask : a.pk_mask;
         const uint32_t dmask = (1u << nbits) - 1u;
         const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;  // wave w owns a contiguous slice
 
@@ -591,7 +593,7 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                         uint64_t w = 0;
 #pragma unroll
                         for (int m = 0; m < R; ++m)
-                            if (m < r) w |= ((uint64_t)c[m][i] & a.pk_mask[m]) << a.pk_pos[m];
+                            if (m < r) w |= ((uint64_t)c[m][i] & pk_mask[m]) << pk_pos[m];
                         s_x[lp[i]] = w;
                     } else {
                         ((CT*)s_x)[lp[i]] = c[0][i];
@@ -609,7 +611,7 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                         uint64_t w = 0;
 #pragma unroll
                         for (int m = 0; m < R; ++m)
-                            if (m < r) w |= ((uint64_t)c[m][i] & a.pk_mask[m]) << a.pk_pos[m];
+                            if (m < r) w |= ((uint64_t)c[m][i] & pk_mask[m]) << pk_pos[m];
                         s_x[lp[i]] = w;
                     } else {
                         ((CT*)s_x)[lp[i]] = c[0][i];
@@ -629,7 +631,7 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                     const uint32_t g = slot_dest(s_dig, s_base, j);
 #pragma unroll
                     for (int m = 0; m < R; ++m)
-                        if (m < r) ((CT*)dst_crd[m])[g] = (CT)((w >> a.pk_pos[m]) & a.pk_mask[m]);
+                        if (m < r) ((CT*)dst_crd[m])[g] = (CT)((w >> pk_pos[m]) & pk_mask[m]);
                 }
             }
             __syncthreads();
@@ -1474,7 +1476,7 @@ hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
     static int resident = 0;
     // packed words in (R = 1 with 64-bit words, or unpacking) and the packing pass: three
     // workgroups per CU
-    if constexpr (MODE == 0 && ITEMS == 16 && ((PK == 1 && QSD_PACK3) || PK == 2 || (R == 1 && sizeof(CT) == 8)))
+    if constexpr (MODE != 1 && ITEMS == 16 && ((PK == 1 && QSD_PACK3) || PK == 2 || (R == 1 && sizeof(CT) == 8)))
         return launch_persistent(k_digit3<R, CT, VT, ITEMS, MODE, PK>, resident, a, s);
     else
         return launch_persistent(k_digit<R, CT, VT, ITEMS, MODE, PK>, resident, a, s);
@@ -1482,7 +1484,11 @@ hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
 
 template <int R, typename CT, typename VT, int ITEMS>
 hipError_t digit_ri(const DigitArgs& a, hipStream_t s) {
-    if (a.seg_mode == 2) return digit_rs<R, CT, VT, ITEMS, 2>(a, s);
+    if (a.seg_mode == 2) {
+        if (a.pk == 1) return digit_rs<R, CT, VT, ITEMS, 2, 1>(a, s);
+        if (a.pk == 2) return digit_rs<R, CT, VT, ITEMS, 2, 2>(a, s);
+        return digit_rs<R, CT, VT, ITEMS, 2>(a, s);
+    }
     if (a.seg_mode == 1) return digit_rs<R, CT, VT, ITEMS, 1>(a, s);
     if (a.pk == 1) return digit_rs<R, CT, VT, ITEMS, 0, 1>(a, s);
     if (a.pk == 2) return digit_rs<R, CT, VT, ITEMS, 0, 2>(a, s);

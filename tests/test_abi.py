@@ -190,3 +190,21 @@ def test_selector_host_parts(lib):
     assert qsd.qsd_mlp_train_workspace(1000, 128) > 1000 * 4
     with pytest.raises(qsd.QsdError):
         qsd.qsd_mlp_train_workspace(10, 0)
+
+
+def test_batch_workspace_max_covers_every_tuning(lib):
+    # a 6-bit key is one pass at digit widths 6-8 but two (and packed records) at 4-5
+    h = qsd.qsd_batch_plan([(2, 100000, [64, 64], 0, 1, (0, 1), (1, 0)),
+                            (3, 50000, [100, 2000, 30], 0, 1, (0, 1, 2), (2, 1, 0)),
+                            (4, 3000, [9, 9, 9, 9], 0, 1, (3, 2, 1, 0), (0, 1, 2, 3))])
+    try:
+        mx = qsd.qsd_batch_workspace_max(h)
+        for rb in (4, 5, 6, 7, 8):
+            for items in (0, 8, 16):
+                for cap in (0, 100, 1024, 4096):
+                    qsd.qsd_batch_set_tuning(h, items, rb, cap)
+                    assert qsd.qsd_batch_workspace(h) <= mx, (items, rb, cap)
+        with pytest.raises(qsd.QsdError):
+            qsd.qsd_batch_set_tuning(h, 12, 8, 0)
+    finally:
+        qsd.qsd_batch_destroy(h)
