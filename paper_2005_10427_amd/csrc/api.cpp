@@ -290,7 +290,7 @@ qsd_status qsd_plan(const qsd_desc* desc, qsd_sched_t sched, qsd_plan_t* out) {
     int passes = 0;
     for (const auto& g : p.groups)
         for (const auto& s : g.subs) passes += (int)s.passes.size();
-    if (passes > 200) {
+    if (passes > kCtlWords - kCtlPassCnt) {  // one tile counter per pass in the control block
         delete q;
         return QSD_ERR_UNSUPPORTED;
     }
