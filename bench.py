@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="plain", choices=["plain", "batched"])
     ap.add_argument("--count", type=int, default=None, help="tensors of the batched workload (testing only)")
+    ap.add_argument("--no-sequence", action="store_true",
+                    help="batched workload: skip timing the one-by-one comparison (for profiler runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="K",
                     help="after timing, run K identity transpositions (plain copies of every array) "
                          "that calibrate hardware byte counters against a known size")
@@ -257,8 +259,10 @@ def bench_batched(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    plain_sec = timed(plain_step, max(1, args.steps // 4))
-    log(f"plain sequence: {plain_sec * 1e3:.3f} ms/step, {N / plain_sec / 1e9:.2f} G nnz/s")
+    plain_sec = None
+    if not args.no_sequence:
+        plain_sec = timed(plain_step, max(1, args.steps // 4))
+        log(f"plain sequence: {plain_sec * 1e3:.3f} ms/step, {N / plain_sec / 1e9:.2f} G nnz/s")
     eager_sec = timed(lambda: B.transpose(stream), args.steps)
     log(f"batched eager: {eager_sec * 1e3:.3f} ms/step")
     sec = timed(lambda: B.replay(stream), args.steps)
@@ -294,10 +298,11 @@ def bench_batched(args):
                                "replay per step",
                    "tensors": len(T), "nnz": N, "tuning": {"items": best[0], "radix_bits": best[1],
                                                            "small_cap": best[2]}},
-        "plain_sequence": {"value": N / plain_sec, "ms_per_step": plain_sec * 1e3,
-                           "schedule": "minimal", "launch": "one qsd_transpose per tensor"},
+        "plain_sequence": None if plain_sec is None else
+        {"value": N / plain_sec, "ms_per_step": plain_sec * 1e3, "schedule": "minimal",
+         "launch": "one qsd_transpose per tensor"},
         "batched_eager_ms_per_step": eager_sec * 1e3,
-        "speedup_vs_plain_sequence": plain_sec / sec,
+        "speedup_vs_plain_sequence": None if plain_sec is None else plain_sec / sec,
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
