@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sched", default="minimal", choices=["minimal", "top2", "lsd", "auto"])
+    ap.add_argument("--keep-buckets", action="store_true",
+                    help="run bucketed groups as segment sorts (QSD_KEEP_BUCKETS) instead of flattening")
     ap.add_argument("--nnz", type=int, default=None, help="shrink the workload (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="plain", choices=["plain", "batched"])
@@ -125,7 +127,8 @@ def main():
     crd = [torch.from_numpy(c).to(dev) for c in T.crd]
     val = torch.from_numpy(T.val).to(dev)
     model = qsd.qsd_model_load(qsd.MODEL_PATH) if args.sched == "auto" else None
-    plans = [qsd.Plan(T.extents, T.in_order, s, N, "int32", "float64", args.sched, model=model, crd=crd)
+    flags = qsd.QSD_KEEP_BUCKETS if args.keep_buckets else 0
+    plans = [qsd.Plan(T.extents, T.in_order, s, N, "int32", "float64", args.sched, flags, model=model, crd=crd)
              for s in sigmas]
     if model is not None:
         log("selector chose " + ", ".join(f"{s}: {qsd.SCHED_NAMES[p.chosen]}" for s, p in zip(sigmas, plans)))
@@ -181,10 +184,27 @@ def main():
         "config": {"workload": "plain: 3-mode COO 500000x20000x2000000, 1e8 distinct nonzeros, "
                                "Zipf(1.1) coordinates, int32 coordinates, fp64 values, input order "
                                "(0,1,2) -> all 5 other orders per step",
-                   "nnz": N, "orders": [list(s) for s in sigmas], "schedule": args.sched},
+                   "nnz": N, "orders": [list(s) for s in sigmas], "schedule": args.sched,
+                   "bucketed_groups": "segment sorts" if args.keep_buckets else "flattened where cheaper"},
         "roofline": roofline,
         "modelled_bytes_per_step": whole_bytes / args.steps,
     }
+    # CSF pack of the last order's output (reported beside the metric, not part of it)
+    csf = None
+    if outs:
+        P = plans[-1]
+        oc = outs[-1][0]
+        P.pack_csf(oc)  # warm-up (allocates its outputs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            _, _, counts = P.pack_csf(oc)
+        sec = (time.perf_counter() - t0) / reps
+        csf = {"order": list(sigmas[-1]), "ms": sec * 1e3, "fiber_counts": counts,
+               "note": "wall time of qsd_pack_csf incl. its output allocation and count read-back"}
+        log(f"CSF pack of sigma={sigmas[-1]}: {sec * 1e3:.3f} ms, fibers {counts}")
+    out["csf_pack"] = csf
     if args.copy_probe:
         ident = qsd.Plan(T.extents, T.in_order, T.in_order, N, "int32", "float64", args.sched)
         oc, ov = outs[0]
