@@ -62,6 +62,10 @@ __device__ __forceinline__ void sync_after_lds_atomics() {
     lds_wait();
     __syncthreads();
 }
+// The value of the lane below (lane 0 gets ~0): a whole-wave DPP shift, no LDS round trip.
+__device__ __forceinline__ uint32_t from_lane_below(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+}
 // number of set bits of m in lanes below this one
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
@@ -172,7 +176,7 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
                     const uint32_t slot = e < hi ? p * kBins + ((uint32_t)(key[u] >> plo[p]) & pmask[p]) : spare;
                     // sorted inputs put long runs of one digit in consecutive lanes: add each
                     // run once, from its first lane, instead of one conflicting atomic per lane
-                    const uint32_t prev = __shfl_up(slot, 1, 64);
+                    const uint32_t prev = from_lane_below(slot);
                     const bool head = (lane == 0) || (prev != slot);
                     const uint64_t heads = ballot(head);
                     if (head) {
@@ -1104,7 +1108,7 @@ __global__ void __launch_bounds__(256) k_hist_batch(BatchHistArgs a) {
                     const uint64_t key = psub[p] ? k1[u] : k0[u];
                     const uint32_t slot = e < end ? p * kBins + ((uint32_t)(key >> plo[p]) & pmask[p]) : spare;
                     // runs of one digit in consecutive lanes are added once, from their first lane
-                    const uint32_t prev = __shfl_up(slot, 1, 64);
+                    const uint32_t prev = from_lane_below(slot);
                     const bool head = (lane == 0) || (prev != slot);
                     const uint64_t heads = ballot(head);
                     if (head) {
