@@ -29,6 +29,9 @@ constexpr uint32_t kCntMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 20;
 // Word 3 of a raw (unformatted, unswizzled) buffer resource on gfx9-family targets.
 constexpr int kBufferWord3 = 0x00020000;
+#ifndef QSD_HIST_U
+#define QSD_HIST_U 8
+#endif
 // Digit-pass schedule choices (compile-time tuning): issue every load of a tile before the
 // ranking, and rank with two interleaved counter chains per wave.
 #ifndef QSD_LOADS_UPFRONT
@@ -131,7 +134,7 @@ __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uin
 // segment.  Also clears the look-back words of the key's first digit pass.
 template <int R, typename CT>
 __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
-    constexpr int U = 8;  // records per thread per round (independent loads in flight)
+    constexpr int U = QSD_HIST_U;  // records per thread per round (independent loads in flight)
     constexpr int MAXP = 16;
     __shared__ uint32_t s_h[MAXP * kBins + kBins];  // + one spare block for out-of-range items
     const int tid = threadIdx.x, lane = tid & 63;
