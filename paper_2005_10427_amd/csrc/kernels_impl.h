@@ -32,6 +32,9 @@ constexpr int kBufferWord3 = 0x00020000;
 #ifndef QSD_HIST_U
 #define QSD_HIST_U 8
 #endif
+#ifndef QSD_HISTB_U
+#define QSD_HISTB_U 8
+#endif
 // Digit-pass schedule choices (compile-time tuning): issue every load of a tile before the
 // ranking, and rank with two interleaved counter chains per wave.
 #ifndef QSD_LOADS_UPFRONT
@@ -1026,7 +1029,7 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
 // look-back words of the first batched launch.
 template <int R, typename CT>
 __global__ void __launch_bounds__(256) k_hist_batch(BatchHistArgs a) {
-    constexpr int U = 8, MAXP = 16;
+    constexpr int U = QSD_HISTB_U, MAXP = 16;
     __shared__ uint32_t s_h[MAXP * kBins + kBins];  // + a spare block for items past the end
     const int tid = threadIdx.x, lane = tid & 63;
     const uint32_t spare = MAXP * kBins;
@@ -1090,11 +1093,14 @@ __global__ void __launch_bounds__(256) k_hist_batch(BatchHistArgs a) {
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 if (!(km[0][m] | km[1][m])) continue;
+                // the index is clamped to the tensor's last record instead of branching, so the
+                // U loads are issued back to back; records past the end are counted into the
+                // spare block below whatever their value
                 CT c[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const uint32_t e = base + u * kBlock + tid;
-                    c[u] = e < end ? src[m][e] : CT(0);
+                    c[u] = src[m][min(e, end - 1u)];
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
