@@ -164,19 +164,17 @@ void make_layout(qsd_plan_s* q) {
     L.total = at;
 }
 
-// Histogram workgroups per CU (loads in flight); QSD_HIST_BLOCKS overrides both for tuning.
-int hist_env_blocks() {
+// Histogram workgroups per CU (loads in flight); QSD_HIST_BLOCKS overrides it for tuning.
+// Measured per CU: one key of 2 modes over 1e8 records: 4 -> 385 us, 8 -> 341, 12 -> 326,
+// 16 -> 319; 4096 tensors, 608M records: 4 -> 3.69 ms, 8 -> 3.13, 12 -> 2.97, 16 -> 2.85.
+int hist_blocks_per_cu() {
     static int v = [] {
         const char* e = std::getenv("QSD_HIST_BLOCKS");
         const int x = e ? std::atoi(e) : 0;
-        return (x >= 1 && x <= 16) ? x : 0;
+        return (x >= 1 && x <= 16) ? x : 16;
     }();
     return v;
 }
-// measured: 4 -> 385 us, 8 -> 341, 12 -> 326 (2 key modes, 1e8 records)
-int hist_blocks_per_cu() { return hist_env_blocks() ? hist_env_blocks() : 12; }
-// measured on 4096 tensors, 608M records: 4 -> 3.69 ms, 8 -> 3.13, 12 -> 2.97, 16 -> 2.85
-int hist_batch_blocks_per_cu() { return hist_env_blocks() ? hist_env_blocks() : 16; }
 
 bool is_perm(const int32_t* o, int r) {
     bool seen[kMaxR] = {};
@@ -1164,7 +1162,7 @@ qsd_status qsd_batch_transpose(qsd_batch_t b, void* ws, size_t ws_bytes, hipStre
         ha.tile = (uint32_t)b->tile;
         ha.status_zero = S[0];
         const int grid = (int)std::max<uint32_t>(
-            1, std::min<uint32_t>(b->total_tiles, (uint32_t)(device_cu_count() * hist_batch_blocks_per_cu())));
+            1, std::min<uint32_t>(b->total_tiles, (uint32_t)(device_cu_count() * hist_blocks_per_cu())));
         QSD_CK(timed(kHistBatch, 0, stream, [&] { return launch_hist_batch(ha, b->rmax, b->crd_bytes, grid, stream); }));
         QSD_CK(timed(kHistBatch, 0, stream, [&] {
             return launch_hist_prefix((uint32_t*)(W + b->off_hist), (uint32_t)(b->hist_words / kBins), stream);
