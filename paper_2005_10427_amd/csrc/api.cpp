@@ -895,10 +895,10 @@ qsd_status batch_derive(qsd_batch_s* b) {
     tb = up(tb + (size_t)b->maxD * nl * sizeof(BatchPass));
     b->tab_map = tb;
     b->map_off.assign(b->launch_tiles.size(), 0);
-    size_t words = 0;
+    size_t words = 0;  // four words per launch tile
     for (size_t l = 0; l < b->launch_tiles.size(); ++l) {
         b->map_off[l] = words;
-        words += b->launch_tiles[l].size();
+        words += 4 * b->launch_tiles[l].size();
     }
     tb = up(tb + words * 4);
     b->tab_job = tb;
@@ -1073,17 +1073,29 @@ qsd_status qsd_batch_bind(qsd_batch_t b, const qsd_batch_io* io, void* ws, size_
                 }
             }
         }
-        for (int kind = 0; kind < kKinds; ++kind) {
-            const size_t l = (size_t)p * kKinds + kind;
-            uint32_t* map = (uint32_t*)(H + b->tab_map) + b->map_off[l];
-            std::copy(b->launch_tiles[l].begin(), b->launch_tiles[l].end(), map);
-        }
     }
     uint32_t* tj = (uint32_t*)(H + b->tab_job);
-    BatchHistJob* hj = (BatchHistJob*)(H + b->tab_hjob);
     for (size_t li = 0; li < nl; ++li) {
         const BTensor& x = b->t[b->large[li]];
         for (uint32_t k = 0; k < x.tiles; ++k) tj[x.tile0 + k] = (uint32_t)li;
+    }
+    // launch tiles: stable tile id, tensor, first record, records
+    for (size_t l = 0; l < b->launch_tiles.size(); ++l) {
+        uint32_t* map = (uint32_t*)(H + b->tab_map) + b->map_off[l];
+        for (size_t j = 0; j < b->launch_tiles[l].size(); ++j) {
+            const uint32_t t = b->launch_tiles[l][j];
+            const uint32_t li = tj[t];
+            const BTensor& x = b->t[b->large[li]];
+            const uint32_t start = (t - x.tile0) * (uint32_t)b->tile;
+            map[4 * j + 0] = t;
+            map[4 * j + 1] = li;
+            map[4 * j + 2] = start;
+            map[4 * j + 3] = std::min<uint32_t>((uint32_t)b->tile, x.n - start);
+        }
+    }
+    BatchHistJob* hj = (BatchHistJob*)(H + b->tab_hjob);
+    for (size_t li = 0; li < nl; ++li) {
+        const BTensor& x = b->t[b->large[li]];
         BatchHistJob& j = hj[li];
         std::memset(&j, 0, sizeof(j));
         for (int m = 0; m < x.r; ++m) j.crd[m] = io[b->large[li]].in_crd[m];
@@ -1184,7 +1196,6 @@ qsd_status qsd_batch_transpose(qsd_batch_t b, void* ws, size_t ws_bytes, hipStre
             da.pk = kind == kKindPack ? 1 : (kind == kKindUnpack ? 2 : 0);
             da.ntiles = (uint32_t)b->launch_tiles[l].size();
             da.tile_map = (const uint32_t*)(T + b->tab_map) + b->map_off[l];
-            da.tile_job = (const uint32_t*)(T + b->tab_job);
             da.batch = (const BatchPass*)(T + b->tab_pass) + (size_t)p * nl;
             da.status = S[p % 2];
             da.status_next = (p + 1 < b->maxD) ? S[(p + 1) % 2] : nullptr;

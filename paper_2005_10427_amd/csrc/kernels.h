@@ -80,9 +80,9 @@ struct DigitArgs {
     uint32_t* tile_counter;
     const uint64_t* large_ctl;  // segment mode
     const SegRec* large;        // segment mode
-    const uint32_t* tile_map;   // segment mode: large segment of every tile;
-                                // batch mode: stable tile id of every launch-local tile
-    const uint32_t* tile_job;   // batch mode: tensor (table entry) of every stable tile
+    const uint32_t* tile_map;   // segment mode: large segment of every tile; batch mode: four
+                                // words per launch tile (stable tile id, tensor, first record,
+                                // records), 16-byte aligned
     const BatchPass* batch;     // batch mode: this launch's table
     uint32_t* err;
     // Packed records (global and batch modes).  pk = 1: read the r coordinate arrays, write one

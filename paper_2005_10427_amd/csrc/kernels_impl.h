@@ -422,12 +422,14 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                 }
             } else if (MODE == 2) {
                 if (lt < ntiles) {
-                    t = a.tile_map[lt];  // stable tile id: the look-back words are indexed by it
-                    k = a.tile_job[t];
-                    const uint32_t t0 = a.batch[k].tile0;
-                    lowest = t0;
-                    start = (t - t0) * TILE;
-                    len = min((uint32_t)TILE, a.batch[k].n - start);
+                    // one load: stable tile id (the look-back words are indexed by it), tensor,
+                    // first record and record count of the launch tile
+                    const uint4 g = reinterpret_cast<const uint4*>(a.tile_map)[lt];
+                    t = g.x;
+                    k = g.y;
+                    start = g.z;
+                    len = g.w;
+                    lowest = t - start / TILE;  // the tensor's first tile
                     live = true;
                 }
             } else if (lt < ntiles) {
