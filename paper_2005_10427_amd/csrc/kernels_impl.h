@@ -72,6 +72,21 @@ __device__ __forceinline__ void sync_after_lds_atomics() {
 __device__ __forceinline__ uint32_t from_lane_below(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
 }
+// One count per lane into s_h[slot].  Consecutive lanes holding the same slot (long runs in
+// sorted inputs) are added once, from the run's first lane, by the run's length, instead of
+// one conflicting atomic per lane.  When every lane starts a run (every run has length 1, the
+// usual case for unsorted digits) each lane adds 1 directly, skipping the run lengths.
+__device__ __forceinline__ void count_slot(uint32_t* s_h, uint32_t slot, int lane) {
+    // lane 0 always starts a run: the value "below" it is ~0, which no slot equals
+    const uint64_t heads = ballot(from_lane_below(slot) != slot);
+    if (heads == ~0ull) {
+        atomicAdd(&s_h[slot], 1u);
+    } else if ((heads >> lane) & 1ull) {
+        const uint64_t after = (heads >> 1) >> lane;  // heads above this lane
+        const uint32_t run = after ? (uint32_t)__builtin_ctzll(after) + 1u : 64u - lane;
+        atomicAdd(&s_h[slot], run);
+    }
+}
 // number of set bits of m in lanes below this one
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
@@ -173,23 +188,16 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
                 for (int u = 0; u < U; ++u)
                     key[u] |= (((uint64_t)c[u] >> a.key.src_lo[m]) & a.key.mask[m]) << a.key.dst[m];
             }
+            bool ok[U];  // records past the end count into the spare block
+#pragma unroll
+            for (int u = 0; u < U; ++u) ok[u] = base + u * kBlock + tid < hi;
 #pragma unroll
             for (int p = 0; p < MAXP; ++p) {
                 if (p >= npass) break;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t e = base + u * kBlock + tid;
-                    const uint32_t slot = e < hi ? p * kBins + ((uint32_t)(key[u] >> plo[p]) & pmask[p]) : spare;
-                    // sorted inputs put long runs of one digit in consecutive lanes: add each
-                    // run once, from its first lane, instead of one conflicting atomic per lane
-                    const uint32_t prev = from_lane_below(slot);
-                    const bool head = (lane == 0) || (prev != slot);
-                    const uint64_t heads = ballot(head);
-                    if (head) {
-                        const uint64_t after = (lane == 63) ? 0ull : (heads >> (lane + 1));
-                        const uint32_t run = after ? (uint32_t)__builtin_ctzll(after) + 1u : 64u - lane;
-                        atomicAdd(&s_h[slot], run);
-                    }
+                    const uint32_t slot = ok[u] ? p * kBins + ((uint32_t)(key[u] >> plo[p]) & pmask[p]) : spare;
+                    count_slot(s_h, slot, lane);
                 }
             }
         }
