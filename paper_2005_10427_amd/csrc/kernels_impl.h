@@ -527,14 +527,20 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                 uint32_t* cnt = (QSD_RANK2 && part) ? s_cnt2 : s_cnt;
                 const bool ok = (wb + i * 64) < len;
                 const uint32_t d = dg[i];
-                uint64_t peers = ballot(ok);
+                // peers: the lanes whose digit equals this lane's, bit by bit.  sm is this lane's
+                // bit b smeared over the word (0 or ~0); a lane j agrees with it on bit b iff
+                // bit j of ~(ballot ^ sm) is set.  Kept as two 32-bit halves.
+                const uint64_t pk0 = ballot(ok);
+                uint32_t plo = (uint32_t)pk0, phi = (uint32_t)(pk0 >> 32);
 #pragma unroll
                 for (int b = 0; b < 8; ++b) {  // digits have at most 8 bits
                     if (b >= nbits) break;
-                    const bool bit = (d >> b) & 1u;
-                    const uint64_t bb = ballot(bit);
-                    peers &= bit ? bb : ~bb;
+                    const uint32_t sm = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+                    const uint64_t bb = ballot(sm != 0u);
+                    plo &= ~((uint32_t)bb ^ sm);
+                    phi &= ~((uint32_t)(bb >> 32) ^ sm);
                 }
+                const uint64_t peers = ((uint64_t)phi << 32) | plo;
                 const uint32_t below = lanes_below(peers);
                 uint32_t old = 0;
                 if (ok) old = cnt[wave * kBins + d];
