@@ -529,12 +529,12 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                 const uint32_t d = dg[i];
                 // peers: the lanes whose digit equals this lane's, bit by bit.  sm is this lane's
                 // bit b smeared over the word (0 or ~0); a lane j agrees with it on bit b iff
-                // bit j of ~(ballot ^ sm) is set.  Kept as two 32-bit halves.
+                // bit j of ~(ballot ^ sm) is set.  Kept as two 32-bit halves.  All 8 bits are
+                // visited: above the pass's width every digit has 0, which leaves the mask as is.
                 const uint64_t pk0 = ballot(ok);
                 uint32_t plo = (uint32_t)pk0, phi = (uint32_t)(pk0 >> 32);
 #pragma unroll
-                for (int b = 0; b < 8; ++b) {  // digits have at most 8 bits
-                    if (b >= nbits) break;
+                for (int b = 0; b < 8; ++b) {
                     const uint32_t sm = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
                     const uint64_t bb = ballot(sm != 0u);
                     plo &= ~((uint32_t)bb ^ sm);
