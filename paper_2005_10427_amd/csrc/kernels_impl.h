@@ -537,8 +537,10 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                 for (int b = 0; b < 8; ++b) {
                     const uint32_t sm = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
                     const uint64_t bb = ballot(sm != 0u);
-                    plo &= ~((uint32_t)bb ^ sm);
-                    phi &= ~((uint32_t)(bb >> 32) ^ sm);
+                    // acc & ~(ballot ^ sm) in one three-input operation per half (truth table
+                    // 0x90: set where acc is set and the other two agree)
+                    plo = __builtin_amdgcn_bitop3_b32(plo, (uint32_t)bb, sm, 0x90);
+                    phi = __builtin_amdgcn_bitop3_b32(phi, (uint32_t)(bb >> 32), sm, 0x90);
                 }
                 const uint64_t peers = ((uint64_t)phi << 32) | plo;
                 const uint32_t below = lanes_below(peers);
