@@ -535,7 +535,8 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                 uint32_t plo = (uint32_t)pk0, phi = (uint32_t)(pk0 >> 32);
 #pragma unroll
                 for (int b = 0; b < 8; ++b) {
-                    const uint32_t sm = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+                    uint32_t sm = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+                    asm("" : "+v"(sm));  // opaque: the ballot then compares sm itself
                     const uint64_t bb = ballot(sm != 0u);
                     // acc & ~(ballot ^ sm) in one three-input operation per half (truth table
                     // 0x90: set where acc is set and the other two agree)
