@@ -74,12 +74,13 @@ __device__ __forceinline__ uint32_t from_lane_below(uint32_t x) {
 }
 // One count per lane into s_h[slot].  Consecutive lanes holding the same slot (long runs in
 // sorted inputs) are added once, from the run's first lane, by the run's length, instead of
-// one conflicting atomic per lane.  When every lane starts a run (every run has length 1, the
-// usual case for unsorted digits) each lane adds 1 directly, skipping the run lengths.
+// one conflicting atomic per lane.  When at least half of the lanes start a run (the usual case
+// for unsorted digits, where the few repeated slots cost the LDS little) each lane adds 1
+// directly, skipping the run lengths.  Either way every lane is counted once.
 __device__ __forceinline__ void count_slot(uint32_t* s_h, uint32_t slot, int lane) {
     // lane 0 always starts a run: the value "below" it is ~0, which no slot equals
     const uint64_t heads = ballot(from_lane_below(slot) != slot);
-    if (heads == ~0ull) {
+    if (__popcll(heads) >= 32) {
         atomicAdd(&s_h[slot], 1u);
     } else if ((heads >> lane) & 1ull) {
         const uint64_t after = (heads >> 1) >> lane;  // heads above this lane
