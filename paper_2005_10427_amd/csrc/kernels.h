@@ -44,6 +44,20 @@ inline int digit_items(int r, int crd_bytes, int val_bytes, int pref = 0) {
     return words <= 6 ? 16 : 8;
 }
 
+// The part of one key mode inside a digit window.  The mode's field occupies bits
+// [dst, dst + width) of the composite key and comes from bits [src_lo, src_lo + width) of the
+// coordinate; the digit is bits [lo, lo + nbits) of the key.  Their overlap is coordinate bits
+// [rs, rs + ln), which land at digit bit ls (ln = 0: the mode adds nothing to this digit).
+struct DigitSlice {
+    uint32_t rs, ln, ls;
+};
+__host__ __device__ inline DigitSlice digit_slice(int dst, int src_lo, int width, int lo, int nbits) {
+    const int a = dst > lo ? dst : lo;
+    const int e = (dst + width) < (lo + nbits) ? (dst + width) : (lo + nbits);
+    if (e <= a) return DigitSlice{0u, 0u, 0u};
+    return DigitSlice{(uint32_t)(src_lo + a - dst), (uint32_t)(e - a), (uint32_t)(a - lo)};
+}
+
 // One tensor's digit pass inside a batched launch (device table, one entry per tensor).
 struct BatchPass {
     const void* src_crd[8];

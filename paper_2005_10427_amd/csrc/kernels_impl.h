@@ -493,14 +493,35 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
 #pragma unroll
             for (int m = 0; m < R; ++m)
                 if (m < r && key.mask[m]) load_items<CT, ITEMS>((const CT*)src_crd[m], start, len, wb, c[m]);
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                uint64_t kv = 0;
+            if constexpr (sizeof(CT) == 4) {
+                // 32-bit coordinates: the digit is assembled from each key mode's slice of the
+                // digit window (one bit-field extract and one shift-or per mode) instead of
+                // building the 64-bit key
+                DigitSlice sl[R];
 #pragma unroll
                 for (int m = 0; m < R; ++m)
-                    if (m < r && key.mask[m])
-                        kv |= (((uint64_t)c[m][i] >> key.src_lo[m]) & key.mask[m]) << key.dst[m];
-                dg[i] = (uint32_t)(kv >> lo_bit) & dmask;
+                    sl[m] = (m < r && key.mask[m])
+                                ? digit_slice(key.dst[m], key.src_lo[m], 64 - __builtin_clzll(key.mask[m]), lo_bit, nbits)
+                                : DigitSlice{0u, 0u, 0u};
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    uint32_t dv = 0;
+#pragma unroll
+                    for (int m = 0; m < R; ++m)
+                        if (m < r && key.mask[m])
+                            dv |= __builtin_amdgcn_ubfe((uint32_t)c[m][i], sl[m].rs, sl[m].ln) << sl[m].ls;
+                    dg[i] = dv;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    uint64_t kv = 0;
+#pragma unroll
+                    for (int m = 0; m < R; ++m)
+                        if (m < r && key.mask[m])
+                            kv |= (((uint64_t)c[m][i] >> key.src_lo[m]) & key.mask[m]) << key.dst[m];
+                    dg[i] = (uint32_t)(kv >> lo_bit) & dmask;
+                }
             }
         }
         if constexpr (QSD_LOADS_UPFRONT) {  // every array in flight before the ranking
