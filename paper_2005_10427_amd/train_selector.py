@@ -289,7 +289,7 @@ def evaluate(model_path, count, seed, out_npz, big=True):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", choices=["collect", "train", "evaluate", "all"])
-    ap.add_argument("--dir", default="gpurun_out/selector")
+    ap.add_argument("--dir", default="selector_runs", help="where collected timings, the trained model and the report are written")
     ap.add_argument("--count", type=int, default=3000)
     ap.add_argument("--eval-count", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=300)
