@@ -1144,9 +1144,10 @@ __global__ void __launch_bounds__(256) k_hist_batch(BatchHistArgs a) {
                     c[u] = src[m][min(e, end - 1u)];
                 }
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    k0[u] |= (((uint64_t)c[u] >> ks[0][m]) & km[0][m]) << kd[0][m];
-                    k1[u] |= (((uint64_t)c[u] >> ks[1][m]) & km[1][m]) << kd[1][m];
+                for (int u = 0; u < U; ++u) k0[u] |= (((uint64_t)c[u] >> ks[0][m]) & km[0][m]) << kd[0][m];
+                if (nsub > 1) {  // keys wider than 64 bits only
+#pragma unroll
+                    for (int u = 0; u < U; ++u) k1[u] |= (((uint64_t)c[u] >> ks[1][m]) & km[1][m]) << kd[1][m];
                 }
             }
 #pragma unroll
