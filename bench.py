@@ -18,6 +18,7 @@ one with the minimal-pass plan.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -76,9 +77,29 @@ def cpu_baseline(T, sigmas, budget_s=20.0):
             break
         n *= 4
     rate = n * len(sigmas) / t_one
+    # a comparison sort costs about N log N: the rate at the full size is lower by log n / log N
+    full = rate * math.log(n) / math.log(T.nnz) if n < T.nnz else rate
     return {"value": rate, "unit": "nnz/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} nonzeros of the workload tensor, all {len(sigmas)} orders, "
-                      f"{t_one:.1f} s single-threaded numpy (lexsort + gather)"}
+            "sample": f"first {n} nonzeros of the {T.nnz}-nonzero workload tensor (a prefix, still "
+                      f"sorted in the input order), all {len(sigmas)} orders, {t_one:.1f} s "
+                      f"single-threaded numpy (lexsort + gather)",
+            "full_size_estimate": {"value": full, "rule": "sample rate x log(sample) / log(nnz)"},
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """The host's CPU model and thread count, as the oracle's rate depends on them."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
 def main():
@@ -157,6 +178,11 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = qsd.qsd_profile_stop()
+    # the status bits accumulate over calls: this covers every timed transposition
+    status = qsd.qsd_device_status(ws.data_ptr(), stream.cuda_stream)
+    if status:
+        log(f"device status {status} after the timed steps")
+        return 1
     sec = t1 - t0
     ms_per_step = 1e3 * sec / args.steps
     value = N * len(sigmas) * args.steps / sec
@@ -234,7 +260,7 @@ def cpu_baseline_batched(T, budget_s=20.0):
         k += 1
     return {"value": done / sec, "unit": "nnz/s", "cores": 1, "kind": "oracle",
             "sample": f"first {k} tensors of the batch ({done} nonzeros), {sec:.1f} s single-threaded "
-                      f"numpy (lexsort + gather)"}
+                      f"numpy (lexsort + gather)", "host": host_cpu()}
 
 
 def bench_batched(args):
@@ -298,6 +324,9 @@ def bench_batched(args):
         B.transpose(stream)
     torch.cuda.synchronize()
     prof = qsd.qsd_profile_stop()
+    if B.device_status():
+        log("device status nonzero after the profiled steps")
+        return 1
     for k, (n_l, ms, b) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
         log(f"  {k:12s} launches={n_l:6d} total={ms:9.3f} ms avg={ms / max(n_l, 1) * 1e3:8.1f} us"
             + (f"  {b / ms / 1e6:8.1f} GB/s" if b and ms else ""))

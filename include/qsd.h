@@ -106,7 +106,9 @@ qsd_status qsd_plan_workspace(qsd_plan_t plan, size_t* bytes);
  */
 qsd_status qsd_plan_describe(qsd_plan_t plan, char* buf, size_t len);
 
-/* Transpose.  in_crd / out_crd: host arrays of r DEVICE pointers (mode order);
+/* Transpose (Sec. 2.2: the same nonzeros re-listed in sigma's lexicographic order; carried
+ * out as the plan's partial sorts, Alg. 1 and Alg. 2, in the order Alg. 3 gives).
+ * in_crd / out_crd: host arrays of r DEVICE pointers (mode order);
  * in_val / out_val: device pointers.  nnz <= planned nnz.  Inputs are read only; outputs
  * must not overlap the inputs or the workspace.  ws: device workspace of ws_bytes >=
  * qsd_plan_workspace.  Asynchronous on `stream`. */
@@ -116,7 +118,9 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz,
                          void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Compressed sparse fiber (CSF) pack of a tensor already sorted under the plan's out_order
- * (e.g. qsd_transpose's output).  Levels d = 1..r store mode sigma_d.  Every level is
+ * (e.g. qsd_transpose's output): the compressed, level-by-level format of Sec. 1-2, whose
+ * level order is the mode order the tensor is sorted in (the reason a transposition is needed
+ * before building it).  Levels d = 1..r store mode sigma_d.  Every level is
  * compressed: level d has F_d fibers (maximal runs sharing sigma_1..sigma_d; at d = r
  * every nonzero is its own leaf, F_r = nnz).
  *   crd[d-1]: device array (crd type) with room for nnz entries; receives F_d coordinates.
@@ -187,9 +191,11 @@ qsd_status qsd_batch_graph(qsd_batch_t batch, void* ws, size_t ws_bytes, qsd_gra
 qsd_status qsd_graph_launch(qsd_graph_t graph, hipStream_t stream);
 void qsd_graph_destroy(qsd_graph_t graph);
 
-/* Device-side status of the last call that used this workspace: 0 when every kernel ran
- * normally, otherwise a bit set (1: a bounded wait in a scan timed out).  Synchronises
- * `stream` and reads 4 bytes.  Validation results are returned by qsd_transpose itself. */
+/* Device-side status of every call that used this workspace since the previous
+ * qsd_device_status on it (or since its first use): 0 when every kernel ran normally,
+ * otherwise the OR of the bits the kernels set (1: a bounded wait in a scan timed out, and the
+ * output of that call is not valid).  Synchronises `stream`, reads 4 bytes and clears them.
+ * Validation results are returned by qsd_transpose itself. */
 qsd_status qsd_device_status(void* ws, hipStream_t stream, uint32_t* code);
 
 const char* qsd_status_str(qsd_status s);

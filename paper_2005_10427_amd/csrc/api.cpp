@@ -90,10 +90,7 @@ void make_layout(qsd_plan_s* q) {
     const PlanData& p = q->p;
     Layout& L = q->L;
     const uint64_t N = (uint64_t)std::max<int64_t>(p.nnz, 1);
-    int pref = 0;
-    if (const char* e = std::getenv("QSD_DIGIT_ITEMS")) pref = std::atoi(e);  // tuning override
-    if (const char* e = std::getenv("QSD_PACK")) q->pack = std::atoi(e) != 0;   // tuning override
-    q->items = digit_items(p.r, p.crd_bytes, p.val_bytes, pref);
+    q->items = digit_items(p.r, p.crd_bytes, p.val_bytes);
     q->tile = kBlock * q->items;
     const uint64_t T = (uint64_t)q->tile;
     size_t at = 0;
@@ -164,17 +161,10 @@ void make_layout(qsd_plan_s* q) {
     L.total = at;
 }
 
-// Histogram workgroups per CU (loads in flight); QSD_HIST_BLOCKS overrides it for tuning.
-// Measured per CU: one key of 2 modes over 1e8 records: 4 -> 385 us, 8 -> 341, 12 -> 326,
-// 16 -> 319; 4096 tensors, 608M records: 4 -> 3.69 ms, 8 -> 3.13, 12 -> 2.97, 16 -> 2.85.
-int hist_blocks_per_cu() {
-    static int v = [] {
-        const char* e = std::getenv("QSD_HIST_BLOCKS");
-        const int x = e ? std::atoi(e) : 0;
-        return (x >= 1 && x <= 16) ? x : 16;
-    }();
-    return v;
-}
+// Histogram workgroups per CU (loads in flight).  Measured per CU: one key of 2 modes over 1e8
+// records: 4 -> 385 us, 8 -> 341, 12 -> 326, 16 -> 319; 4096 tensors, 608M records: 4 -> 3.69 ms,
+// 8 -> 3.13, 12 -> 2.97, 16 -> 2.85.
+int hist_blocks_per_cu() { return 16; }
 
 bool is_perm(const int32_t* o, int r) {
     bool seen[kMaxR] = {};
@@ -362,8 +352,7 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
 
     {
         ZeroArgs z{};
-        z.ptr[0] = ctl;
-        z.words[0] = kCtlWords;
+        z.ctl = ctl;
         if (L.hist_words) {
             z.ptr[1] = (uint32_t*)(W + L.hist);
             z.words[1] = L.hist_words;
@@ -678,9 +667,16 @@ qsd_status qsd_profile_stop(qsd_kernel_stat* out, int32_t max, int32_t* count) {
 
 qsd_status qsd_device_status(void* ws, hipStream_t stream, uint32_t* code) {
     if (!ws || !code) return QSD_ERR_NULL;
-    if (hipMemcpyAsync(code, (char*)ws + kCtlErr * 4, 4, hipMemcpyDeviceToHost, stream) != hipSuccess)
+    static const uint32_t zero = 0;
+    uint32_t word = 0;
+    if (hipMemcpyAsync(&word, (char*)ws + kCtlErr * 4, 4, hipMemcpyDeviceToHost, stream) != hipSuccess)
         return QSD_ERR_HIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return QSD_ERR_HIP;
+    // read and clear: the bits accumulate until the host has seen them
+    if (hipMemcpyAsync((char*)ws + kCtlErr * 4, &zero, 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return QSD_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return QSD_ERR_HIP;
+    *code = word;
     return QSD_OK;
 }
 
@@ -708,8 +704,7 @@ qsd_status qsd_pack_csf(qsd_plan_t plan, int64_t nnz, const void* const* sorted_
     uint32_t* st = (uint32_t*)(W + up(kCtlWords * 4));
     const uint64_t tiles = cdiv(std::max<uint32_t>(n, 1), kBlock * 8);
     ZeroArgs z{};
-    z.ptr[0] = ctl;
-    z.words[0] = kCtlWords;
+    z.ctl = ctl;
     z.ptr[1] = st;
     z.words[1] = tiles * 8;
     if (timed(kZero, 0, stream, [&] { return launch_zero(z, stream); }) != hipSuccess) return QSD_ERR_HIP;
@@ -937,8 +932,6 @@ qsd_status qsd_batch_plan(const qsd_desc* descs, int32_t count, qsd_batch_t* out
             delete b;
             return QSD_ERR_UNSUPPORTED;
         }
-        if (i == 0)
-            if (const char* e = std::getenv("QSD_PACK")) b->pack = std::atoi(e) != 0;  // tuning override
         BTensor x;
         x.r = descs[i].order;
         x.n = (uint32_t)descs[i].nnz;
@@ -1159,8 +1152,7 @@ qsd_status qsd_batch_transpose(qsd_batch_t b, void* ws, size_t ws_bytes, hipStre
         if ((e = (x)) != hipSuccess) return QSD_ERR_HIP; \
     } while (0)
     ZeroArgs z{};
-    z.ptr[0] = ctl;
-    z.words[0] = kCtlWords;
+    z.ctl = ctl;
     if (b->hist_words) {
         z.ptr[1] = (uint32_t*)(W + b->off_hist);
         z.words[1] = b->hist_words;

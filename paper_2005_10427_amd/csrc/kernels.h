@@ -23,8 +23,13 @@ enum CtlSlot {
     kCtlNMed = 3,       // medium segments
     kCtlLarge = 4,      // uint64 at words 4-5: (large segments << 32) | large tiles
     kCtlBoundCnt = 8,   // tile counter of the boundary scan
-    kCtlPassCnt = 16,   // 256 tile counters, one per digit pass launch
+    kCtlMagic = 9,      // kCtlStickyMagic once kCtlErr holds accumulated status bits
+    kCtlPassCnt = 16,   // tile counters, one per digit pass launch
 };
+// The status bits of kCtlErr accumulate over calls (the library clears them when the host reads
+// them).  A fresh workspace holds arbitrary bytes: the first call that finds the magic word
+// missing clears the bits and writes it.
+constexpr uint32_t kCtlStickyMagic = 0x51534431u;
 
 struct DevKey {
     uint64_t mask[8];
@@ -207,6 +212,7 @@ struct SmallArgs {
 struct ZeroArgs {
     uint32_t* ptr[4];
     uint64_t words[4];
+    uint32_t* ctl;              // control block: every word cleared except kCtlErr / kCtlMagic
 };
 
 struct ValidateArgs {

@@ -54,7 +54,7 @@ int device_cu_count() {
 }
 
 hipError_t launch_zero(const ZeroArgs& a, hipStream_t s) {
-    uint64_t mx = 0;
+    uint64_t mx = a.ctl ? kCtlWords : 0;
     for (int i = 0; i < 4; ++i)
         if (a.ptr[i]) mx = std::max(mx, a.words[i]);
     const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((mx + 255) / 256, 2048));

@@ -29,28 +29,7 @@ constexpr uint32_t kCntMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 20;
 // Word 3 of a raw (unformatted, unswizzled) buffer resource on gfx9-family targets.
 constexpr int kBufferWord3 = 0x00020000;
-#ifndef QSD_HIST_U
-#define QSD_HIST_U 8
-#endif
-#ifndef QSD_HISTB_U
-#define QSD_HISTB_U 8
-#endif
-// Digit-pass schedule choices (compile-time tuning): issue every load of a tile before the
-// ranking, and rank with two interleaved counter chains per wave.
-#ifndef QSD_LOADS_UPFRONT
-#define QSD_LOADS_UPFRONT 0
-#endif
-#ifndef QSD_RANK2
-#define QSD_RANK2 1
-#endif
-// Run the look-back after the tile-local work that does not need its result.
-#ifndef QSD_LATE_LOOKBACK
-#define QSD_LATE_LOOKBACK 0
-#endif
-// The packing pass also at three workgroups per CU (a few registers spill).
-#ifndef QSD_PACK3
-#define QSD_PACK3 0
-#endif
+constexpr int kHistU = 8;   // records per thread per round of a histogram (loads in flight)
 constexpr int kWaves = kBlock / 64;
 
 __device__ __forceinline__ uint32_t ld_status(const uint32_t* p) {
@@ -131,6 +110,14 @@ __device__ __forceinline__ uint64_t compose_key(const CT (&c)[8], const DevKey& 
 // ------------------------------------------------------------------------------ utility
 
 __global__ void __launch_bounds__(256) k_zero(ZeroArgs a) {
+    if (a.ctl) {
+        for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < (uint32_t)kCtlWords; i += gridDim.x * 256u)
+            if (i != kCtlErr && i != kCtlMagic) a.ctl[i] = 0;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && a.ctl[kCtlMagic] != kCtlStickyMagic) {
+            a.ctl[kCtlErr] = 0;
+            a.ctl[kCtlMagic] = kCtlStickyMagic;
+        }
+    }
     for (int r = 0; r < 4; ++r) {
         uint32_t* p = a.ptr[r];
         if (!p) continue;
@@ -153,7 +140,7 @@ __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uin
 // segment.  Also clears the look-back words of the key's first digit pass.
 template <int R, typename CT>
 __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
-    constexpr int U = QSD_HIST_U;  // records per thread per round (independent loads in flight)
+    constexpr int U = kHistU;
     constexpr int MAXP = 16;
     __shared__ uint32_t s_h[MAXP * kBins + kBins];  // + one spare block for out-of-range items
     const int tid = threadIdx.x, lane = tid & 63;
@@ -256,10 +243,7 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
 
 // ------------------------------------------------------------------------------ digit pass
 
-#ifndef QSD_LOOK_WIN
-#define QSD_LOOK_WIN 8
-#endif
-constexpr int kLookWin = QSD_LOOK_WIN;
+constexpr int kLookWin = 8;  // status words read per look-back round trip
 
 // Decoupled look-back done by one whole wave for one counter: lane l reads the status of
 // tile j - l, so 64 predecessors are inspected per round trip.  Statuses are at
@@ -351,19 +335,26 @@ __device__ __forceinline__ uint32_t look_back(const uint32_t* status, uint32_t t
 template <typename T, int ITEMS>
 __device__ __forceinline__ void load_items(const T* __restrict__ src, uint32_t start, uint32_t len,
                                            uint32_t wb, T (&x)[ITEMS]) {
-    // A buffer resource over exactly this tile's records: one offset register per thread, the
-    // per-item offsets in scalar registers, and the hardware range check returns 0 past `len`.
+    // A buffer resource over exactly this tile's records (len * sizeof(T) bytes from record
+    // `start`).  The whole byte offset of every item, (wb + 64 i) * sizeof(T), goes into the
+    // range-checked operands (the vector offset, with the compiler free to move a constant of up
+    // to 4095 bytes into the instruction offset); the scalar offset, which the hardware range
+    // check does not cover on gfx9-family targets, is always 0.  A load at or past `len` returns 0
+    // without touching memory, so no access leaves records [start, start + len).
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void*)(src + start), 0, (int)(len * sizeof(T)), kBufferWord3);
-    const int voff = (int)(wb * sizeof(T));
+    int voff = (int)(wb * sizeof(T));
+    // kept opaque per call so that the per-item constants stay beside their loads, where they
+    // fold into the instruction offset, instead of being hoisted into one register per item
+    asm volatile("" : "+v"(voff));
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const int soff = i * 64 * (int)sizeof(T);
+        const int off = voff + i * 64 * (int)sizeof(T);
         if constexpr (sizeof(T) == 8) {
-            const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
+            const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
             x[i] = (T)(((uint64_t)w[1] << 32) | w[0]);
         } else {
-            x[i] = (T)__builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0);
+            x[i] = (T)__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
         }
     }
 }
@@ -402,7 +393,7 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
     constexpr int TILE = kBlock * ITEMS;
     __shared__ uint64_t s_x[TILE];               // record exchange (4- or 8-byte words)
     __shared__ uint32_t s_cnt[kWaves * kBins];   // per-wave digit counters, then wave prefixes
-    __shared__ uint32_t s_cnt2[QSD_RANK2 ? kWaves * kBins : 1];  // second half of each wave's items
+    __shared__ uint32_t s_cnt2[kWaves * kBins];  // second half of each wave's items
     __shared__ uint32_t s_tstart[kBins];         // first local slot of each digit
     __shared__ uint32_t s_base[kBins];           // global slot of local slot 0 of each digit
     __shared__ uint8_t s_dig[TILE];
@@ -524,29 +515,21 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                 }
             }
         }
-        if constexpr (QSD_LOADS_UPFRONT) {  // every array in flight before the ranking
-            if constexpr (!UNPACK) {
-#pragma unroll
-                for (int m = 0; m < R; ++m)
-                    if (m < r && !key.mask[m]) load_items<CT, ITEMS>((const CT*)src_crd[m], start, len, wb, c[m]);
-            }
-            load_items<VT, ITEMS>((const VT*)src_val, start, len, wb, v);
-        }
 
-        // ---- stable rank inside each wave: ballot-match the digit, count lanes below.  With
-        // two counter sets, the first and second halves of a wave's items form two independent
+        // ---- stable rank inside each wave: ballot-match the digit, count lanes below.  Two
+        // counter sets: the first and second halves of a wave's items form two independent
         // read-modify-write chains on LDS; the second half then adds the first half's totals.
         for (int b = lane; b < kBins; b += 64) {
             s_cnt[wave * kBins + b] = 0;
-            if constexpr (QSD_RANK2) s_cnt2[wave * kBins + b] = 0;
+            s_cnt2[wave * kBins + b] = 0;
         }
-        constexpr int kHalf = QSD_RANK2 ? ITEMS / 2 : ITEMS;
+        constexpr int kHalf = ITEMS / 2;
 #pragma unroll
         for (int h = 0; h < kHalf; ++h) {
 #pragma unroll
-            for (int part = 0; part < (QSD_RANK2 ? 2 : 1); ++part) {
+            for (int part = 0; part < 2; ++part) {
                 const int i = part * kHalf + h;
-                uint32_t* cnt = (QSD_RANK2 && part) ? s_cnt2 : s_cnt;
+                uint32_t* cnt = part ? s_cnt2 : s_cnt;
                 const bool ok = (wb + i * 64) < len;
                 const uint32_t d = dg[i];
                 // peers: the lanes whose digit equals this lane's, bit by bit.  sm is this lane's
@@ -573,17 +556,14 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                 if (ok && below == 0) cnt[wave * kBins + d] = old + (uint32_t)__popcll(peers);
             }
         }
-        if constexpr (QSD_RANK2) {
 #pragma unroll
-            for (int i = kHalf; i < ITEMS; ++i)
-                if ((wb + i * 64) < len) lp[i] += s_cnt[wave * kBins + dg[i]];
-            for (int b = lane; b < kBins; b += 64) s_cnt[wave * kBins + b] += s_cnt2[wave * kBins + b];
-        }
+        for (int i = kHalf; i < ITEMS; ++i)
+            if ((wb + i * 64) < len) lp[i] += s_cnt[wave * kBins + dg[i]];
+        for (int b = lane; b < kBins; b += 64) s_cnt[wave * kBins + b] += s_cnt2[wave * kBins + b];
         __syncthreads();
 
         // ---- per digit: wave prefixes, tile count and the tile-local digit starts; the tile's
         // counts are published at once
-        constexpr bool kEarly = QSD_LATE_LOOKBACK && (UNPACK || (!PACK && R == 1));
         uint32_t tcnt, tstart, hstart;  // of digit b = tid
         {
             const uint32_t b = tid;
@@ -597,15 +577,12 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
             tcnt = run;
             st_status(&a.status[(size_t)t * kBins + b], (first ? kFlagP : kFlagA) | tcnt);
             // the rest of the records, in flight during the scans and the look-back
-            if constexpr (!QSD_LOADS_UPFRONT) {
-                if constexpr (!UNPACK) {
+            if constexpr (!UNPACK) {
 #pragma unroll
-                    for (int m = 0; m < R; ++m)
-                        if (m < r && !key.mask[m])
-                            load_items<CT, ITEMS>((const CT*)src_crd[m], start, len, wb, c[m]);
-                }
-                load_items<VT, ITEMS>((const VT*)src_val, start, len, wb, v);
+                for (int m = 0; m < R; ++m)
+                    if (m < r && !key.mask[m]) load_items<CT, ITEMS>((const CT*)src_crd[m], start, len, wb, c[m]);
             }
+            load_items<VT, ITEMS>((const VT*)src_val, start, len, wb, v);
             tstart = block_excl_scan(tcnt, s_tmp, nullptr);
             // one segment: computed once per workgroup; batch: offsets stored by k_hist_prefix
             hstart = MODE == 0   ? s_hpre[b]
@@ -614,7 +591,7 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
             s_tstart[b] = tstart;
         }
         // ---- the global offset of every digit: decoupled look-back over the predecessors
-        auto global_offsets = [&]() {
+        {
             const uint32_t b = tid;
             uint32_t excl = 0;
             if (!first) {
@@ -623,54 +600,31 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
             }
             s_base[b] = seg_base + hstart + excl - tstart;
             if (a.status_next) a.status_next[(size_t)t * kBins + b] = 0;
-        };
-        if constexpr (!QSD_LATE_LOOKBACK) global_offsets();
+        }
         __syncthreads();
 
         // ---- local slot of every record and the digit of every local slot; the first array is
-        // staged in LDS by local slot in the same sweep when it is already in registers.  None of
-        // this needs the global offsets, so the look-back runs after it, giving the predecessors
-        // time to publish their prefixes.
+        // staged in LDS by local slot in the same sweep (it is already in registers)
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             if ((wb + i * 64) < len) {
                 const uint32_t d = dg[i];
                 lp[i] += s_tstart[d] + s_cnt[wave * kBins + d];
                 s_dig[lp[i]] = (uint8_t)d;
-                if constexpr (!QSD_LATE_LOOKBACK || kEarly) {
-                    if constexpr (UNPACK) {
-                        s_x[lp[i]] = pw[i];
-                    } else if constexpr (PACK) {
-                        uint64_t w = 0;
+                if constexpr (UNPACK) {
+                    s_x[lp[i]] = pw[i];
+                } else if constexpr (PACK) {
+                    uint64_t w = 0;
 #pragma unroll
-                        for (int m = 0; m < R; ++m)
-                            if (m < r) w |= ((uint64_t)c[m][i] & pk_mask[m]) << pk_pos[m];
-                        s_x[lp[i]] = w;
-                    } else {
-                        ((CT*)s_x)[lp[i]] = c[0][i];
-                    }
+                    for (int m = 0; m < R; ++m)
+                        if (m < r) w |= ((uint64_t)c[m][i] & pk_mask[m]) << pk_pos[m];
+                    s_x[lp[i]] = w;
+                } else {
+                    ((CT*)s_x)[lp[i]] = c[0][i];
                 }
             }
         }
-        if constexpr (QSD_LATE_LOOKBACK) global_offsets();
         __syncthreads();
-        if constexpr (QSD_LATE_LOOKBACK && !kEarly) {  // first array staged now that it has arrived
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                if ((wb + i * 64) < len) {
-                    if constexpr (PACK) {
-                        uint64_t w = 0;
-#pragma unroll
-                        for (int m = 0; m < R; ++m)
-                            if (m < r) w |= ((uint64_t)c[m][i] & pk_mask[m]) << pk_pos[m];
-                        s_x[lp[i]] = w;
-                    } else {
-                        ((CT*)s_x)[lp[i]] = c[0][i];
-                    }
-                }
-            }
-            __syncthreads();
-        }
 
         // ---- move every array through LDS: contiguous runs per digit on the way out
         if constexpr (UNPACK) {
@@ -1070,7 +1024,7 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
 // look-back words of the first batched launch.
 template <int R, typename CT>
 __global__ void __launch_bounds__(256) k_hist_batch(BatchHistArgs a) {
-    constexpr int U = QSD_HISTB_U, MAXP = 16;
+    constexpr int U = kHistU, MAXP = 16;
     __shared__ uint32_t s_h[MAXP * kBins + kBins];  // + a spare block for items past the end
     const int tid = threadIdx.x, lane = tid & 63;
     const uint32_t spare = MAXP * kBins;
@@ -1531,7 +1485,7 @@ hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
     static int resident = 0;
     // packed words in (R = 1 with 64-bit words, or unpacking) and the packing pass: three
     // workgroups per CU
-    if constexpr (MODE != 1 && ITEMS == 16 && ((PK == 1 && QSD_PACK3) || PK == 2 || (R == 1 && sizeof(CT) == 8)))
+    if constexpr (MODE != 1 && ITEMS == 16 && (PK == 2 || (R == 1 && sizeof(CT) == 8)))
         return launch_persistent(k_digit3<R, CT, VT, ITEMS, MODE, PK>, resident, a, s);
     else
         return launch_persistent(k_digit<R, CT, VT, ITEMS, MODE, PK>, resident, a, s);

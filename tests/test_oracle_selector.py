@@ -200,3 +200,26 @@ def test_features_identity_and_ranges():
         assert f.shape == (32,) and np.all(np.isfinite(f)) and np.all(f >= 0)
         if sigma == (0, 1, 2):
             assert f[22] == f[23] == f[24] == f[25] == 0
+
+
+def _mix64_int(z):
+    """SplitMix64's output function with Python integers (independent of the numpy oracle)."""
+    m = (1 << 64) - 1
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def test_features_against_hand_derived_golden():
+    """All 32 features of a 6-nonzero 3-mode tensor with sigma = (0, 2, 1), whose slots are not
+    in mode order, against values derived by hand from the feature definitions."""
+    from conftest import read_golden
+    g = read_golden("features_3mode.txt")
+    want = np.array([float(g[str(i)][0]) for i in range(32)])
+    nz = [(0, 1, 1), (0, 1, 4), (1, 1, 0), (1, 1, 3), (1, 2, 0), (3, 2, 2)]
+    crd = [np.array([t[m] for t in nz], dtype=np.int32) for m in range(3)]
+    # the derivation's premise: values 0..4 share no bitmap bit and no bucket
+    h = [_mix64_int(v) for v in range(5)]
+    assert len({x & 0xFFFF for x in h}) == 5 and len({(x >> 16) & 1023 for x in h}) == 5
+    f = F.features(crd, (9, 3, 20), (0, 1, 2), (0, 2, 1))
+    np.testing.assert_allclose(f, want, rtol=1e-12, atol=0)
