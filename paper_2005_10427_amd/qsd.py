@@ -481,11 +481,16 @@ class Plan:
         qsd_transpose(self.handle, n, [c.data_ptr() for c in crd], val.data_ptr(),
                       [c.data_ptr() for c in out_crd], out_val.data_ptr(), ws.data_ptr(), self.ws_bytes,
                       s.cuda_stream)
+        self._last_ws = ws
         return out_crd, out_val
 
     def device_status(self, stream=None):
+        """Status bits of the calls since the last read, on the workspace the last call used."""
         s = stream if stream is not None else self.torch.cuda.current_stream()
-        return qsd_device_status(self.workspace().data_ptr(), s.cuda_stream)
+        ws = getattr(self, "_last_ws", None)
+        if ws is None:
+            return 0  # nothing has run
+        return qsd_device_status(ws.data_ptr(), s.cuda_stream)
 
     def pack_csf(self, sorted_crd, nnz=None, stream=None):
         """CSF of a tensor sorted under out_order: returns (pos list, crd list, fiber counts)."""

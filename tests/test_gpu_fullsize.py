@@ -1,11 +1,15 @@
-"""Full-size transpositions (the 1e8-nonzero 3-mode and 2e8-nonzero 4-mode workloads, in the
-launch configuration the benchmark times) checked through properties that fix the output:
-the nonzeros are distinct, so the stable sort under sigma is the unique sorted arrangement.
-  * sorted: the composite sigma key strictly increases along the output;
-  * same nonzeros: an order-independent hash of every (coordinates, value bits) record is
-    equal on both sides;
-  * positions: at sampled output positions j the record has exactly j input keys below its
-    key (its rank by definition), computed one position at a time."""
+"""Full-size transpositions in the launch configuration the benchmark times:
+  * the 1e8-nonzero 3-mode tensor, all 5 orders, and the 2e8-nonzero 4-mode tensor, all 23
+    orders;
+  * the 4096-tensor batch (about 6e8 nonzeros), autotuned and replayed as one HIP graph;
+  * the 1.5e8-nonzero 5-mode tensor of the selector's held-out set, every schedule.
+The CPU oracle cannot sort these in test time, so the outputs are pinned by
+  * properties that fix them: sorted under sigma (strictly, where the nonzeros are distinct),
+    the same multiset of (coordinates, value bits) by an order-independent hash, and at sampled
+    output positions j the record's rank, computed one position at a time;
+  * an independent stable sort on the GPU (PyTorch's stable argsort, one pass per mode, least
+    significant first) compared array by array, bit for bit;
+  * the CPU oracle, bit for bit, on every 16th tensor of the batch."""
 import sys
 
 import numpy as np
@@ -41,53 +45,198 @@ def _record_hash(crd, val, torch):
     return int(h.sum().item())
 
 
-def _key(crd, sigma, extents, torch):
-    key = torch.zeros_like(crd[0], dtype=torch.int64)
+def _adjacent_order(crd, sigma, torch):
+    """(lt, eq) for every adjacent pair of records: record j < record j+1 under sigma's
+    lexicographic order, and all sigma coordinates equal (keys of any width)."""
+    n = crd[0].shape[0]
+    lt = torch.zeros(max(n - 1, 0), dtype=torch.bool, device=crd[0].device)
+    eq = torch.ones_like(lt)
     for m in sigma:
-        b = (int(extents[m]) - 1).bit_length() if extents[m] > 1 else 0
-        key = (key << b) | crd[m].to(torch.int64)
-    return key
+        a, b = crd[m][:-1], crd[m][1:]
+        lt |= eq & (a < b)
+        eq &= a == b
+    return lt, eq
 
 
-def _check_full(qsd, name, sigmas, samples=512):
+def _count_below(crd, sigma, rec, torch):
+    """Records whose sigma tuple is below / equal to the tuple `rec` (one value per mode)."""
+    lt = torch.zeros_like(crd[0], dtype=torch.bool)
+    eq = torch.ones_like(lt)
+    for m in sigma:
+        lt |= eq & (crd[m] < rec[m])
+        eq &= crd[m] == rec[m]
+    return int(lt.sum().item()), int(eq.sum().item())
+
+
+def _stable_reference(crd, val, sigma, torch):
+    """The stable sort under sigma by PyTorch's stable argsort, one pass per mode (LSD)."""
+    idx = torch.arange(crd[0].shape[0], device=crd[0].device)
+    for m in reversed(sigma):
+        idx = idx[torch.argsort(crd[m][idx], stable=True)]
+    return [c[idx] for c in crd], val[idx]
+
+
+def _bits_equal(a, b, torch):
+    if a.dtype == torch.float64:
+        return torch.equal(a.view(torch.int64), b.view(torch.int64))
+    if a.dtype == torch.float32:
+        return torch.equal(a.view(torch.int32), b.view(torch.int32))
+    return torch.equal(a, b)
+
+
+def _check_one(P, crd, val, sigma, out_crd, out_val, h_in, g, samples, distinct, torch, reference=True):
+    n = val.shape[0]
+    lt, eq = _adjacent_order(out_crd, sigma, torch)
+    if distinct:
+        assert bool(lt.all()), "output not strictly sorted under sigma"
+    else:
+        assert bool((lt | eq).all()), "output not sorted under sigma"
+    del lt, eq
+    assert _record_hash(out_crd, out_val, torch) == h_in, "records differ"
+    pos = torch.randint(0, n, (samples,), generator=g, device=crd[0].device)
+    pos[0], pos[1] = 0, n - 1
+    for j in pos.tolist():
+        rec = [int(c[j].item()) for c in out_crd]
+        below, same = _count_below(crd, sigma, rec, torch)
+        assert below <= j < below + same, (sigma, j, below, same)
+        if distinct:
+            assert below == j and same == 1, (sigma, j)
+    if reference:
+        w_crd, w_val = _stable_reference(crd, val, sigma, torch)
+        for m in range(len(crd)):
+            assert torch.equal(out_crd[m], w_crd[m]), (sigma, "mode", m)
+        assert _bits_equal(out_val, w_val, torch), (sigma, "values")
+        del w_crd, w_val
+
+
+@pytest.fixture(scope="module")
+def plain_full():
     import torch
-    note(f"generating {name} at full size")
-    T = config_tensor(name)
+    note("generating plain at full size")
+    T = config_tensor("plain")
+    dev = torch.device("cuda:0")
+    crd = [torch.from_numpy(c).to(dev) for c in T.crd]
+    val = torch.from_numpy(T.val).to(dev)
+    yield T, crd, val
+    del crd, val
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def wide_full():
+    import torch
+    note("generating wide at full size")
+    T = config_tensor("wide")
     dev = torch.device("cuda:0")
     crd = [torch.from_numpy(c).to(dev) for c in T.crd]
     val = torch.from_numpy(T.val).to(dev)
     del T.crd[:]
+    yield T, crd, val
+    del crd, val
+    torch.cuda.empty_cache()
+
+
+def _check_full(qsd, name, data, sigmas, samples, sched="minimal"):
+    import torch
+    T, crd, val = data
+    dev = crd[0].device
     h_in = _record_hash(crd, val, torch)
-    plans = [qsd.Plan(T.extents, T.in_order, s, val.shape[0], str(crd[0].dtype).replace("torch.", ""),
-                      str(val.dtype).replace("torch.", ""), "minimal") for s in sigmas]
+    cd = str(crd[0].dtype).replace("torch.", "")
+    vd = str(val.dtype).replace("torch.", "")
+    plans = [qsd.Plan(T.extents, T.in_order, s, val.shape[0], cd, vd, sched) for s in sigmas]
     ws = torch.empty(max(p.ws_bytes for p in plans), dtype=torch.uint8, device=dev)
     out_crd = [torch.empty_like(c) for c in crd]
     out_val = torch.empty_like(val)
     g = torch.Generator(device=dev)
     g.manual_seed(20050427)
-    n = val.shape[0]
     for P, sigma in zip(plans, sigmas):
-        note(f"{name} sigma={sigma}")
+        note(f"{name} sigma={sigma} {sched}")
         P.transpose(crd, val, out_crd, out_val, ws=ws)
         torch.cuda.synchronize()
         assert P.device_status() == 0
-        k_out = _key(out_crd, sigma, P.extents, torch)
-        assert bool((k_out[1:] > k_out[:-1]).all()), "output not strictly sorted under sigma"
-        assert _record_hash(out_crd, out_val, torch) == h_in, "records differ"
-        k_in = _key(crd, sigma, P.extents, torch)
-        pos = torch.randint(0, n, (samples,), generator=g, device=dev)
-        pos[0], pos[1] = 0, n - 1
-        for j in pos.tolist():
-            assert int((k_in < k_out[j]).sum().item()) == j, (sigma, j)
-        del k_in, k_out
+        _check_one(P, crd, val, sigma, out_crd, out_val, h_in, g, samples, True, torch)
+    del ws, out_crd, out_val
 
 
-def test_plain_full_size(gpu_lib):
-    _check_full(gpu_lib, "plain", CONFIGS["plain"]["sigmas"], samples=256)
+def test_plain_full_size(gpu_lib, plain_full):
+    _check_full(gpu_lib, "plain", plain_full, CONFIGS["plain"]["sigmas"], samples=128)
 
 
-def test_wide_full_size(gpu_lib):
-    # the orders whose plans differ most: bucketed groups kept or flattened, two-pass groups,
-    # packed and unpacked paths
-    sig = CONFIGS["wide"]["sigmas"]
-    _check_full(gpu_lib, "wide", sig[::4], samples=64)
+WIDE = CONFIGS["wide"]["sigmas"]
+
+
+@pytest.mark.parametrize("part", range(4))
+def test_wide_full_size(gpu_lib, wide_full, part):
+    # all 23 orders, in four groups (bucketed groups flattened or kept, two-pass groups,
+    # packed and unpacked paths all occur)
+    _check_full(gpu_lib, "wide", wide_full, WIDE[part::4], samples=32)
+
+
+def test_batched_full_size(gpu_lib):
+    """The 4096-tensor batch: autotuned, captured, one replay; every tensor checked against
+    the independent stable sort and by its properties, every 16th against the CPU oracle."""
+    import torch
+    from datagen.batched import BATCHED, make_batch
+    from oracle.transpose import transpose as oracle_transpose
+    note("generating the 4096-tensor batch")
+    T = make_batch(device="cuda", **BATCHED)
+    torch.cuda.synchronize()
+    note(f"{len(T)} tensors, {sum(t.nnz for t in T)} nonzeros")
+    B = gpu_lib.Batch([t.as_dict() for t in T])
+    best, ms = B.tune(reps=1)
+    note(f"tuned {best} {ms:.2f} ms")
+    B.capture()
+    for oc, ov in zip(B.out_crd, B.out_val):
+        ov.fill_(7.0)
+        for c in oc:
+            c.fill_(-1)
+    B.replay()
+    torch.cuda.synchronize()
+    assert B.device_status() == 0
+    g = torch.Generator(device="cuda")
+    g.manual_seed(20050427 + 3)
+    for i, t in enumerate(T):
+        if t.nnz == 0:
+            continue
+        oc, ov = B.out_crd[i], B.out_val[i]
+        h_in = _record_hash(t.crd, t.val, torch)
+        _check_one(None, t.crd, t.val, t.out_order, oc, ov, h_in, g, 2, False, torch)
+        if i % 16 == 0:
+            w_crd, w_val = oracle_transpose([c.cpu().numpy() for c in t.crd], t.val.cpu().numpy(), t.out_order)
+            for m in range(len(w_crd)):
+                assert np.array_equal(oc[m].cpu().numpy(), w_crd[m]), (i, m)
+            assert np.array_equal(ov.cpu().numpy().view(np.uint64), w_val.view(np.uint64)), (i, "values")
+        if i % 512 == 0:
+            note(f"batch tensor {i} ok")
+
+
+@pytest.fixture(scope="module")
+def heldout_5mode():
+    import torch
+    from datagen.batched import make_batch
+    from paper_2005_10427_amd.train_selector import BIG
+    note("generating the 5-mode tensor")
+    t = make_batch(0, seed=20050427 + 5, device="cuda", extra=[BIG])[0]
+    torch.cuda.synchronize()
+    yield t
+    del t
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("sched", ["minimal", "top2", "lsd"])
+def test_heldout_5mode_full_size(gpu_lib, heldout_5mode, sched):
+    """The 2e6 x 3e5 x 5e4 x 2e3 x 100 tensor with 1.5e8 nonzeros (74-bit keys, duplicates
+    possible) of the selector's held-out set, each schedule."""
+    import torch
+    t = heldout_5mode
+    crd, val = t.crd, t.val
+    note(f"5-mode tensor, {sched}")
+    h_in = _record_hash(crd, val, torch)
+    P = gpu_lib.Plan(t.extents, t.in_order, t.out_order, t.nnz, "int32", "float64", sched)
+    out_crd, out_val = P.transpose(crd, val)
+    torch.cuda.synchronize()
+    assert P.device_status() == 0
+    g = torch.Generator(device="cuda")
+    g.manual_seed(20050427 + 5)
+    _check_one(P, crd, val, t.out_order, out_crd, out_val, h_in, g, 32, False, torch)
+    del out_crd, out_val
