@@ -117,6 +117,22 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz,
                          void* const* out_crd, void* out_val,
                          void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* qsd_transpose without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).  The
+ * workspace is a fixed array of QSD_NOALLOC_MAX_WORKSPACE bytes in device memory that the
+ * library holds on every GPU it runs on until the process ends; the call allocates nothing.
+ * Plans whose qsd_plan_workspace exceeds that size are rejected with QSD_ERR_WORKSPACE before
+ * anything is launched (for 3-mode int32/fp64 tensors about 1.8M planned nonzeros fit).
+ * `stream` must belong to the GPU to run on (NULL: the current device).  All calls on one GPU
+ * share its array, which keeps the last call's contents (each call clears what must start at
+ * zero): calls that overlap on one GPU race and must not be issued.  The device status bits of
+ * these calls cannot be read back (qsd_device_status needs a workspace pointer).  Other
+ * arguments, errors and semantics as qsd_transpose. */
+#define QSD_NOALLOC_MAX_WORKSPACE ((size_t)64 << 20)
+qsd_status qsd_transpose_noalloc(qsd_plan_t plan, int64_t nnz,
+                                 const void* const* in_crd, const void* in_val,
+                                 void* const* out_crd, void* out_val, hipStream_t stream);
+
 /* Compressed sparse fiber (CSF) pack of a tensor already sorted under the plan's out_order
  * (e.g. qsd_transpose's output): the compressed, level-by-level format of Sec. 1-2, whose
  * level order is the mode order the tensor is sorted in (the reason a transposition is needed

@@ -17,6 +17,8 @@ QSD_F32, QSD_F64 = 0, 1
 SCHED = {"auto": 0, "minimal": 1, "top2": 2, "lsd": 3}
 QSD_VALIDATE = 1
 QSD_KEEP_BUCKETS = 2
+QSD_ERR_WORKSPACE = 7
+QSD_NOALLOC_MAX_WORKSPACE = 64 << 20  # as declared in qsd.h
 MAX_ORDER = 8
 
 
@@ -66,6 +68,8 @@ def load():
     lib.qsd_plan_describe.argtypes = [_VP, ctypes.c_char_p, ctypes.c_size_t]
     lib.qsd_transpose.argtypes = [_VP, ctypes.c_int64, ctypes.POINTER(_VP), _VP, ctypes.POINTER(_VP), _VP,
                                   _VP, ctypes.c_size_t, _VP]
+    lib.qsd_transpose_noalloc.argtypes = [_VP, ctypes.c_int64, ctypes.POINTER(_VP), _VP, ctypes.POINTER(_VP), _VP,
+                                          _VP]
     lib.qsd_csf_workspace.argtypes = [_VP, ctypes.POINTER(ctypes.c_size_t)]
     lib.qsd_pack_csf.argtypes = [_VP, ctypes.c_int64, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                                  ctypes.POINTER(_VP), _VP, _VP, ctypes.c_size_t, _VP]
@@ -118,7 +122,7 @@ def load():
                  "qsd_mlp_backward_workspace", "qsd_mlp_backward", "qsd_mlp_adam", "qsd_mlp_train_workspace",
                  "qsd_mlp_train", "qsd_model_create", "qsd_model_load", "qsd_select", "qsd_plan_auto"):
         getattr(lib, name).restype = ctypes.c_int
-    for name in ("qsd_plan", "qsd_plan_workspace", "qsd_plan_describe", "qsd_transpose",
+    for name in ("qsd_plan", "qsd_plan_workspace", "qsd_plan_describe", "qsd_transpose", "qsd_transpose_noalloc",
                  "qsd_csf_workspace", "qsd_pack_csf", "qsd_device_status", "qsd_profile_start",
                  "qsd_profile_stop", "qsd_batch_plan", "qsd_batch_set_tuning", "qsd_batch_get_tuning",
                  "qsd_batch_workspace", "qsd_batch_workspace_max", "qsd_batch_bind", "qsd_batch_transpose",
@@ -180,6 +184,12 @@ def qsd_transpose(plan, nnz, in_crd, in_val, out_crd, out_val, ws, ws_bytes, str
     """in_crd/out_crd: sequences of device pointers (ints); others device pointers/ints."""
     _check(load().qsd_transpose(plan, int(nnz), _ptrs(in_crd), in_val, _ptrs(out_crd), out_val,
                                 ws, int(ws_bytes), stream), "qsd_transpose")
+
+
+def qsd_transpose_noalloc(plan, nnz, in_crd, in_val, out_crd, out_val, stream):
+    """qsd_transpose on the library's fixed per-GPU workspace (no allocation)."""
+    _check(load().qsd_transpose_noalloc(plan, int(nnz), _ptrs(in_crd), in_val, _ptrs(out_crd), out_val, stream),
+           "qsd_transpose_noalloc")
 
 
 def qsd_csf_workspace(plan):
