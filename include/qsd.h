@@ -57,16 +57,20 @@ typedef enum qsd_value_t { QSD_F32 = 0, QSD_F64 = 1 } qsd_value_t;
 /* Pass schedules; every schedule produces the identical output.
  * MINIMAL: QuesadillaSort (Alg. 3, Sec. 3.5) -- the provably minimal number of partial
  *          sorts, bucketed ones only where necessary (Thm 3.4, Thm 3.5).
- * TOP2:    Top-K-sadilla (Sec. 3.6) with K = min(2, r-2): MINIMAL towards
+ * TOPK + K (1 <= K <= r-1): Top-K-sadilla (Sec. 3.6): MINIMAL towards
  *          (sigma_1..sigma_K, remaining modes in input order), then every bucket of equal
- *          (sigma_1..sigma_K) sorted completely.
+ *          (sigma_1..sigma_K) sorted completely on the rest of sigma.  K = r-1 plans exactly
+ *          what MINIMAL plans (the last mode never needs a sort of its own).
+ * TOP2:    TOPK with K = min(2, r-2): Top-1 for 3 modes, Top-2 from 4 modes on.
  * LSD:     full least-significant-digit radix sort over all r modes (the paper's "radix").
- * AUTO:    a learned cost model picks one of the three (MINIMAL when no model is loaded). */
+ * AUTO:    a learned cost model picks among the candidates of qsd_select.h (MINIMAL when no
+ *          model is loaded). */
 typedef enum qsd_sched_t {
     QSD_SCHED_AUTO = 0,
     QSD_SCHED_MINIMAL = 1,
     QSD_SCHED_TOP2 = 2,
-    QSD_SCHED_LSD = 3
+    QSD_SCHED_LSD = 3,
+    QSD_SCHED_TOPK = 16         /* QSD_SCHED_TOPK + K selects Top-K-sadilla with that K */
 } qsd_sched_t;
 
 #define QSD_VALIDATE 1u   /* qsd_transpose checks ranges and input order first (synchronises) */

@@ -32,6 +32,7 @@ struct Layout {
     size_t seg_start = 0, region_seg = 0, bstatus = 0, bstatus_words = 0, med = 0, large = 0, seg_hist = 0;
     size_t tile_map = 0;
     size_t pk[2] = {};        // packed-record ping-pong buffers (64-bit words)
+    size_t seg_bits = 0;      // segment starts as one bit per record (bucket reuse)
     uint32_t max_large = 0, max_med = 0, max_tiles_large = 0;
     size_t total = 0;
 };
@@ -45,6 +46,7 @@ struct HopPlan {
 struct qsd_plan_s {
     PlanData p;
     Layout L;
+    std::vector<char> reuse;           // per group: derives its segment starts from the previous group's
     int tile = 0;
     int items = 16;
     bool pack = true;                  // pack records inside global groups when they fit
@@ -150,6 +152,22 @@ void make_layout(qsd_plan_s* q) {
         at = up(at + (size_t)L.max_large * sizeof(SegRec));
         L.seg_hist = at;
         at = up(at + (size_t)L.max_large * max_seg_passes * kBins * 4);
+    }
+    // bucket reuse (Sec. 5): a segmented group right after a segmented group whose kept prefix
+    // its own extends finds its segment starts from the previous ones plus the added modes
+    q->reuse.assign(p.groups.size(), 0);
+    bool any_reuse = false;
+    for (size_t i = 1; i < p.groups.size(); ++i) {
+        const Group &a = p.groups[i - 1], &b = p.groups[i];
+        if (a.segmented && b.segmented && a.prefix.size() < b.prefix.size() &&
+            std::equal(a.prefix.begin(), a.prefix.end(), b.prefix.begin())) {
+            q->reuse[i] = 1;
+            any_reuse = true;
+        }
+    }
+    if (any_reuse) {
+        L.seg_bits = at;
+        at = up(at + cdiv(N, 64) * 8);
     }
     bool any_pack = false;
     for (const auto& g : p.groups) any_pack |= packable(q, g);
@@ -271,7 +289,9 @@ qsd_status qsd_plan(const qsd_desc* desc, qsd_sched_t sched, qsd_plan_t* out) {
     *out = nullptr;
     const qsd_status st = check_desc(desc);
     if (st != QSD_OK) return st;
-    if (sched < QSD_SCHED_AUTO || sched > QSD_SCHED_LSD) return QSD_ERR_UNSUPPORTED;
+    const int si = (int)sched;
+    if (!((si >= QSD_SCHED_AUTO && si <= QSD_SCHED_LSD) || (si > QSD_SCHED_TOPK && si < QSD_SCHED_TOPK + desc->order)))
+        return QSD_ERR_UNSUPPORTED;
     auto* q = new qsd_plan_s();
     PlanData& p = q->p;
     p.r = desc->order;
@@ -318,6 +338,7 @@ qsd_status qsd_plan_describe(qsd_plan_t plan, char* buf, size_t len) {
          " seg_start=" + std::to_string(L.seg_start) + " region_seg=" + std::to_string(L.region_seg) +
          " tile_map=" + std::to_string(L.tile_map) + " med=" + std::to_string(L.med) +
          " large=" + std::to_string(L.large) + " seg_hist=" + std::to_string(L.seg_hist) +
+         " seg_bits=" + std::to_string(L.seg_bits) + " reuse=" + std::to_string(std::count(plan->reuse.begin(), plan->reuse.end(), 1)) +
          " total=" + std::to_string(L.total) + "\n";
     if (len == 0) return QSD_OK;
     const size_t n = std::min(len - 1, s.size());
@@ -406,8 +427,9 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
     auto hop_dst = [&](int h) -> Bufs { return ((H - 1 - h) % 2 == 0) ? outb : wsb; };
 
     Bufs cur = in;
-    int h = 0, q = 0, gsub = 0, gseg = 0;
+    int h = 0, q = 0, gsub = 0, gseg = 0, gi = -1;
     for (const auto& g : p.groups) {
+        ++gi;
         if (!g.segmented) {
             for (const auto& sk : g.subs) {
                 const int np = (int)sk.passes.size();
@@ -526,6 +548,12 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
         for (int m = 0; m < p.r; ++m) ba.crd[m] = gsrc.crd[m];
         ba.nprefix = (int)g.prefix.size();
         for (int i = 0; i < ba.nprefix; ++i) ba.prefix[i] = g.prefix[i];
+        uint64_t* seg_bits = (uint64_t*)(W + L.seg_bits);
+        if (plan->reuse[gi]) {
+            ba.prev_bits = seg_bits;
+            ba.nskip = (int)p.groups[gi - 1].prefix.size();
+        }
+        if ((size_t)gi + 1 < p.groups.size() && plan->reuse[gi + 1]) ba.bits_out = seg_bits;
         ba.n = n;
         ba.seg_start = seg_start;
         ba.region_seg = region_seg;

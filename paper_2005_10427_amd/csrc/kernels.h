@@ -171,6 +171,13 @@ struct BoundArgs {
     const void* crd[8];
     int32_t nprefix;
     int32_t prefix[8];
+    // Bucket reuse: when the previous group kept a prefix that this group's prefix extends,
+    // its segment starts are still segment starts here.  prev_bits (one bit per record, set at
+    // the previous group's segment starts) stands for the comparison of the first nskip prefix
+    // modes.  bits_out (may alias prev_bits) receives this group's starts the same way.
+    const uint64_t* prev_bits;
+    int32_t nskip;
+    uint64_t* bits_out;
     uint32_t n;
     uint32_t* seg_start;        // nb + 1 entries written (seg_start[nb] = n)
     uint32_t* region_seg;       // first segment starting in each kRegion-wide region (+ nb)

@@ -699,7 +699,16 @@ __global__ void __launch_bounds__(256) k_boundary(BoundArgs a) {
     bool f[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) f[i] = (start + wb + i * 64 == 0);
-    for (int j = 0; j < a.nprefix; ++j) {  // all loads of one prefix mode in flight together
+    if (a.prev_bits) {  // the previous group's segment starts: one word per 64 records
+        const uint32_t w0 = (start + (uint32_t)wave * 64u * ITEMS) / 64u;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t off = wb + i * 64;
+            const uint64_t w = off < len ? a.prev_bits[w0 + i] : 0ull;
+            f[i] |= ((w >> lane) & 1ull) != 0;
+        }
+    }
+    for (int j = a.prev_bits ? a.nskip : 0; j < a.nprefix; ++j) {  // all loads of one prefix mode in flight together
         const CT* p = (const CT*)a.crd[a.prefix[j]];
         CT cur[ITEMS], prv[ITEMS];
 #pragma unroll
@@ -718,6 +727,12 @@ __global__ void __launch_bounds__(256) k_boundary(BoundArgs a) {
     for (int i = 0; i < ITEMS; ++i) {
         flags[i] = ballot(f[i] && (wb + i * 64 < len));
         wcount += (uint32_t)__popcll(flags[i]);
+    }
+    if (a.bits_out && lane == 0) {
+        const uint32_t w0 = (start + (uint32_t)wave * 64u * ITEMS) / 64u;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if ((uint32_t)wave * 64u * ITEMS + i * 64 < len) a.bits_out[w0 + i] = flags[i];
     }
     if (lane == 0) s_wsum[wave] = wcount;
     __syncthreads();

@@ -171,6 +171,34 @@ std::vector<Call> quesadilla_calls(int r, const int* in_order, const int* out_or
     return calls;
 }
 
+// Top-K-sadilla (Sec. 3.6): QuesadillaSort towards sigma^K = (sigma_1..sigma_K, the other modes
+// in input order), then every bucket of equal (sigma_1..sigma_K) sorted completely.
+void topk(PlanData& p, int K, std::vector<RawGroup>* raw) {
+    const int r = p.r;
+    p.K = K;
+    int target[kMaxR];
+    int n = 0;
+    for (int i = 0; i < K; ++i) target[n++] = p.out_order[i];
+    for (int i = 0; i < r; ++i) {
+        const int m = p.in_order[i];
+        bool head = false;
+        for (int j = 0; j < K; ++j) head |= (p.out_order[j] == m);
+        if (!head) target[n++] = m;
+    }
+    alg3(r, p.in_order, target, &p.calls, raw);
+    // Inside a bucket of equal (sigma_1..sigma_K) the other modes are in input order, so a
+    // stable sort on sigma_{K+1}..sigma_q finishes the bucket, where sigma_{q+1}..sigma_r is the
+    // longest tail that is already in input order.
+    int pos[kMaxR];
+    for (int i = 0; i < r; ++i) pos[p.in_order[i]] = i;
+    int q = r - 1;  // first mode of the in-order tail; a single last mode always is
+    while (q - 1 >= K && pos[p.out_order[q - 1]] < pos[p.out_order[q]]) --q;
+    RawGroup tail;
+    tail.prefix.assign(p.out_order, p.out_order + K);
+    tail.keys.assign(p.out_order + K, p.out_order + q);
+    if (!tail.keys.empty()) raw->push_back(tail);
+}
+
 bool build_plan(PlanData& p, int sched) {
     if (sched == kSchedAuto) sched = kSchedMinimal;
     p.sched = sched;
@@ -182,29 +210,9 @@ bool build_plan(PlanData& p, int sched) {
         p.K = 0;
         alg3(r, p.in_order, p.out_order, &p.calls, &raw);
     } else if (sched == kSchedTop2) {
-        const int K = std::max(0, std::min(2, r - 2));
-        p.K = K;
-        int target[kMaxR];
-        int n = 0;
-        for (int i = 0; i < K; ++i) target[n++] = p.out_order[i];
-        for (int i = 0; i < r; ++i) {
-            const int m = p.in_order[i];
-            bool head = false;
-            for (int j = 0; j < K; ++j) head |= (p.out_order[j] == m);
-            if (!head) target[n++] = m;
-        }
-        alg3(r, p.in_order, target, &p.calls, &raw);
-        // Inside a bucket of equal (sigma_1..sigma_K) the other modes are in input order, so
-        // a stable sort on sigma_{K+1}..sigma_q finishes the bucket, where sigma_{q+1}..sigma_r
-        // is the longest tail that is already in input order.
-        int pos[kMaxR];
-        for (int i = 0; i < r; ++i) pos[p.in_order[i]] = i;
-        int q = r - 1;  // first mode of the in-order tail; a single last mode always is
-        while (q - 1 >= K && pos[p.out_order[q - 1]] < pos[p.out_order[q]]) --q;
-        RawGroup tail;
-        tail.prefix.assign(p.out_order, p.out_order + K);
-        tail.keys.assign(p.out_order + K, p.out_order + q);
-        if (!tail.keys.empty()) raw.push_back(tail);
+        topk(p, std::max(0, std::min(2, r - 2)), &raw);
+    } else if (sched > kSchedTopK && sched < kSchedTopK + r) {
+        topk(p, sched - kSchedTopK, &raw);
     } else if (sched == kSchedLsd) {
         p.K = 0;
         RawGroup g;
@@ -230,7 +238,8 @@ static std::string join(const std::vector<int>& v) {
 
 std::string describe(const PlanData& p) {
     static const char* names[] = {"AUTO", "MINIMAL", "TOP2", "LSD"};
-    std::string s = std::string("sched=") + names[p.sched] + " K=" + std::to_string(p.K) + "\n";
+    const std::string name = p.sched >= kSchedTopK ? "TOPK" : names[p.sched];
+    std::string s = "sched=" + name + " K=" + std::to_string(p.K) + "\n";
     for (const auto& c : p.calls)
         s += "call prefix=" + join(c.prefix) + " mode=" + std::to_string(c.mode) + "\n";
     for (const auto& g : p.groups) {

@@ -57,7 +57,7 @@ struct Group {
     KeySpec local_key{};       // whole key in one word, for in-LDS segment sorts
 };
 
-enum Sched { kSchedAuto = 0, kSchedMinimal = 1, kSchedTop2 = 2, kSchedLsd = 3 };
+enum Sched { kSchedAuto = 0, kSchedMinimal = 1, kSchedTop2 = 2, kSchedLsd = 3, kSchedTopK = 16 };
 
 struct PlanData {
     int r = 0;
@@ -69,7 +69,7 @@ struct PlanData {
     int out_order[kMaxR] = {};
     uint32_t flags = 0;
     int sched = kSchedMinimal;
-    int K = 0;                 // Top-K depth (TOP2 only)
+    int K = 0;                 // Top-K depth (TOP2 and TOPK + K)
     int radix_bits = 8;        // digit width of global passes
     std::vector<Call> calls;   // QuesadillaSort calls (towards the Top-K target for TOP2)
     std::vector<Group> groups; // execution order

@@ -15,6 +15,16 @@ STATUS = {0: "ok", 1: "null", 2: "bad order", 3: "bad extent", 4: "too large", 5
 QSD_I32, QSD_I64 = 0, 1
 QSD_F32, QSD_F64 = 0, 1
 SCHED = {"auto": 0, "minimal": 1, "top2": 2, "lsd": 3}
+QSD_SCHED_TOPK = 16  # + K: Top-K-sadilla with that K
+
+
+def sched_code(sched):
+    """Schedule code from a name ("minimal", "top2", "lsd", "auto", "topk<K>") or an int."""
+    if not isinstance(sched, str):
+        return int(sched)
+    if sched.startswith("topk"):
+        return QSD_SCHED_TOPK + int(sched[4:])
+    return SCHED[sched]
 QSD_VALIDATE = 1
 QSD_KEEP_BUCKETS = 2
 QSD_ERR_WORKSPACE = 7
@@ -151,7 +161,7 @@ def qsd_plan(order, nnz, extents, crd_type, val_type, in_order, out_order, sched
     lib = load()
     d, _keep = _desc(order, nnz, extents, crd_type, val_type, in_order, out_order, flags)
     h = _VP()
-    _check(lib.qsd_plan(ctypes.byref(d), SCHED[sched] if isinstance(sched, str) else int(sched),
+    _check(lib.qsd_plan(ctypes.byref(d), sched_code(sched),
                         ctypes.byref(h)), "qsd_plan")
     return h.value
 

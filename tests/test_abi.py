@@ -96,6 +96,55 @@ def test_top2_and_lsd_plans(lib, r):
             assert len(groups) == 1 and groups[0]["prefix"] == ""
 
 
+@pytest.mark.parametrize("r", [2, 3, 4, 5])
+def test_every_topk_plan_equals_oracle(lib, r):
+    """Top-K-sadilla for every K = 1..r-1 (Sec. 3.6): the Quesadilla calls towards sigma^K equal
+    the oracle's, the last group sorts each (sigma_1..sigma_K) bucket on the rest of sigma
+    that is not already in input order, and K = r-1 plans what MINIMAL plans."""
+    for K in range(1, r):
+        for tau in itertools.permutations(range(r)):
+            for sigma in itertools.permutations(range(r)):
+                head, calls, groups = _plan(r, tau, sigma, f"topk{K}")
+                assert head["sched"] == "TOPK" and int(head["K"]) == K
+                want, _ = planner.topk_plan(tau, sigma, K)
+                assert calls == want, (K, tau, sigma)
+                pos = {m: i for i, m in enumerate(tau)}
+                q = r - 1
+                while q - 1 >= K and pos[sigma[q - 1]] < pos[sigma[q]]:
+                    q -= 1
+                tail = list(sigma[K:q])
+                if tail:
+                    assert groups[-1]["prefix"] == ",".join(str(m) for m in sigma[:K])
+                    assert groups[-1]["keys"] == ",".join(str(m) for m in tail)
+                if K == r - 1:
+                    _, mcalls, mgroups = _plan(r, tau, sigma, "minimal")
+                    assert calls == mcalls and groups == mgroups
+    for bad in (0, r):
+        with pytest.raises(qsd.QsdError):
+            qsd.qsd_plan(r, 10, [7] * r, qsd.QSD_I32, qsd.QSD_F64, tuple(range(r)), tuple(range(r)), f"topk{bad}")
+
+
+def test_bucket_reuse_is_planned_between_nested_segmented_groups(lib):
+    # (0,2,1,4,3): groups (0)[2] and (0,2,1)[4], both kept as bucket sorts; the second extends
+    # the first's prefix, so it reuses its segment starts
+    h = qsd.qsd_plan(5, 1000, [40, 300, 50, 2000, 30], qsd.QSD_I32, qsd.QSD_F64, (0, 1, 2, 3, 4), (0, 2, 1, 4, 3),
+                     "minimal", qsd.QSD_KEEP_BUCKETS)
+    try:
+        d = qsd.qsd_plan_describe(h)
+    finally:
+        qsd.qsd_plan_destroy(h)
+    _, calls, groups = _parse(d.split("layout")[0])
+    assert [g["prefix"] for g in groups] == ["0", "0,2,1"]
+    assert "reuse=1" in d
+    # a plain group in between (or none before) gives nothing to reuse
+    h = qsd.qsd_plan(4, 1000, [40, 300, 50, 2000], qsd.QSD_I32, qsd.QSD_F64, (0, 1, 2, 3), (1, 0, 3, 2),
+                     "minimal", qsd.QSD_KEEP_BUCKETS)
+    try:
+        assert "reuse=0" in qsd.qsd_plan_describe(h)
+    finally:
+        qsd.qsd_plan_destroy(h)
+
+
 def test_digit_split_covers_key_bits(lib):
     # 3-mode workload with 19/15/21-bit modes: (2,1,0) sorts modes 1 then 2 -> 36 key bits
     head, calls, groups = _plan(3, (0, 1, 2), (2, 1, 0), "minimal", extents=[500000, 20000, 2000000])

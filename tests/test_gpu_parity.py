@@ -83,6 +83,50 @@ def test_wide_config_shrunk_all_orders(gpu_lib):
             check(gpu_lib, T, sigma, sched, cv)
 
 
+@pytest.mark.parametrize("r", [2, 3, 4, 5])
+def test_every_topk_schedule(gpu_lib, r):
+    """Top-K-sadilla for every K = 1..r-1 (Sec. 3.6) on tensors with duplicates, both ways of
+    running bucketed groups."""
+    rng = np.random.default_rng(40 + r)
+    ext = tuple(int(x) for x in rng.integers(3, 3000, size=r))
+    tau = tuple(int(x) for x in rng.permutation(r))
+    T = make_tensor(ext, 60000, zipf=[1.0] * r, in_order=tau, seed=77 + r, distinct=False)
+    cv = dev(T)
+    sigmas = list(itertools.permutations(range(r)))
+    for sigma in (sigmas if r <= 4 else sigmas[::3]):
+        for K in range(1, r):
+            check(gpu_lib, T, sigma, f"topk{K}", cv)
+
+
+def test_bucket_reuse_between_segmented_groups(gpu_lib):
+    """A segmented group right after one whose kept prefix it extends takes its segment starts
+    from the previous group's plus the added prefix modes (Sec. 5's reuse of buckets): 5-mode
+    minimal plans and Top-K plans with such group pairs, buckets kept."""
+    import torch
+    ext = (40, 300, 50, 2000, 30)
+    T = make_tensor(ext, 50000, zipf=[1.1] * 5, in_order=(0, 1, 2, 3, 4), seed=5, distinct=False)
+    cv = dev(T)
+    cases = [((0, 2, 1, 4, 3), "minimal"), ((0, 3, 1, 4, 2), "minimal"), ((0, 4, 1, 3, 2), "minimal")]
+    for sigma in itertools.permutations(range(5)):
+        for K in (2, 3):
+            P = gpu_lib.Plan(ext, T.in_order, sigma, T.nnz, "int32", "float64", f"topk{K}", gpu_lib.QSD_KEEP_BUCKETS)
+            if "reuse=0" not in P.describe() and len(cases) < 12:
+                cases.append((sigma, f"topk{K}"))
+    for sigma, sched in cases:
+        P = gpu_lib.Plan(ext, T.in_order, sigma, T.nnz, "int32", "float64", sched, gpu_lib.QSD_KEEP_BUCKETS)
+        assert "reuse=0" not in P.describe(), (sigma, sched)
+        check(gpu_lib, T, sigma, sched, cv, flags=gpu_lib.QSD_KEEP_BUCKETS)
+    del torch
+
+
+def test_topk_on_the_wide_workload(gpu_lib):
+    T = config_tensor("wide", nnz=200_000)
+    cv = dev(T)
+    for sigma in CONFIGS["wide"]["sigmas"][1::3]:
+        for K in (1, 2):
+            check(gpu_lib, T, sigma, f"topk{K}", cv)
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 2047, 2048, 2049, 4095, 4096, 4097, 8193, 3 * 4096 - 1, 20000])
 def test_ragged_sizes_with_duplicates(gpu_lib, n):
     rng = np.random.default_rng(n)
