@@ -152,7 +152,7 @@ def main():
     plans = [qsd.Plan(T.extents, T.in_order, s, N, "int32", "float64", args.sched, flags, model=model, crd=crd)
              for s in sigmas]
     if model is not None:
-        log("selector chose " + ", ".join(f"{s}: {qsd.SCHED_NAMES[p.chosen]}" for s, p in zip(sigmas, plans)))
+        log("selector chose " + ", ".join(f"{s}: {qsd.CAND_NAMES[p.chosen]}" for s, p in zip(sigmas, plans)))
     ws = torch.empty(max(p.ws_bytes for p in plans), dtype=torch.uint8, device=dev)
     outs = [([torch.empty_like(c) for c in crd], torch.empty_like(val)) for _ in sigmas]
     stream = torch.cuda.current_stream(dev)
@@ -305,10 +305,23 @@ def bench_batched(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    plain_sec = None
+    plain_sec = plain_graph_sec = None
     if not args.no_sequence:
         plain_sec = timed(plain_step, max(1, args.steps // 4))
         log(f"plain sequence: {plain_sec * 1e3:.3f} ms/step, {N / plain_sec / 1e9:.2f} G nnz/s")
+        # the stronger baseline: the same one-by-one sequence captured into one HIP graph, so
+        # that host launch overhead is gone and only the per-tensor kernels remain
+        cap = torch.cuda.Stream()
+        graph = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=cap):
+            for i, (p, t) in enumerate(zip(plans, T)):
+                if t.nnz:
+                    p.transpose(t.crd, t.val, out[0][i], out[1][i], stream=cap, ws=ws)
+        plain_graph_sec = timed(graph.replay, max(1, args.steps // 4))
+        log(f"plain sequence as one graph: {plain_graph_sec * 1e3:.3f} ms/step, "
+            f"{N / plain_graph_sec / 1e9:.2f} G nnz/s")
+        del graph
     eager_sec = timed(lambda: B.transpose(stream), args.steps)
     log(f"batched eager: {eager_sec * 1e3:.3f} ms/step")
     sec = timed(lambda: B.replay(stream), args.steps)
@@ -350,8 +363,12 @@ def bench_batched(args):
         "plain_sequence": None if plain_sec is None else
         {"value": N / plain_sec, "ms_per_step": plain_sec * 1e3, "schedule": "minimal",
          "launch": "one qsd_transpose per tensor"},
+        "plain_sequence_graph": None if plain_graph_sec is None else
+        {"value": N / plain_graph_sec, "ms_per_step": plain_graph_sec * 1e3, "schedule": "minimal",
+         "launch": "one qsd_transpose per tensor, the whole sequence captured into one HIP graph"},
         "batched_eager_ms_per_step": eager_sec * 1e3,
         "speedup_vs_plain_sequence": None if plain_sec is None else plain_sec / sec,
+        "speedup_vs_plain_sequence_graph": None if plain_graph_sec is None else plain_graph_sec / sec,
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -154,6 +154,24 @@ qsd_status qsd_pack_csf(qsd_plan_t plan, int64_t nnz, const void* const* sorted_
                         void* const* pos, void* const* crd, int64_t* fiber_counts,
                         void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* CSF -> CSF transposition (Sec. 5's proposal of transposing the compressed format without a
+ * separate conversion step).  Input: a tensor of nnz leaves in the CSF layout above for the
+ * plan's in_order (level d stores mode in_order[d-1]; in_pos[d-1] / in_crd[d-1] as pos / crd
+ * of qsd_pack_csf, in_val in leaf order), well formed as qsd_pack_csf writes it (reads are
+ * bounded by the fiber counts that the arrays themselves give).  Output: the same tensor in
+ * the CSF layout for the plan's out_order (out_pos / out_crd / fiber_counts as qsd_pack_csf,
+ * out_val in leaf order).  The expansion to coordinates is one scan per level over the
+ * leaves (each leaf's ancestor at level d is the number of level-d fibers whose first leaf is
+ * at or before it, minus one); the leaf level is used as it is; then the plan's passes and the
+ * pack run on the workspace.  ws: device workspace of qsd_csf_transpose_workspace bytes; its
+ * device status is read with qsd_device_status(ws).  Asynchronous on `stream` (the pack's
+ * empty-input path synchronises, as qsd_pack_csf's). */
+qsd_status qsd_csf_transpose_workspace(qsd_plan_t plan, size_t* bytes);
+qsd_status qsd_csf_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_pos,
+                             const void* const* in_crd, const void* in_val, void* const* out_pos,
+                             void* const* out_crd, void* out_val, int64_t* fiber_counts,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------------------
  * Batched transposition: many independent tensors (uneven nnz, orders and mode orders) in a
  * handful of kernel launches that can be captured into one HIP graph.  All tensors of a batch

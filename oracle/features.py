@@ -1,4 +1,4 @@
-"""Oracle: the 32 features the schedule selector reads.  TEST INFRASTRUCTURE ONLY.
+"""Oracle: the 40 features the schedule selector reads.  TEST INFRASTRUCTURE ONLY.
 
 The features describe what the paper identifies as the drivers of run time: how many
 passes a plan makes and how many of them are bucketed (Sec. 3.4-3.6, Sec. 5), the bit widths
@@ -6,6 +6,15 @@ of the sorted modes (large extents make the count arrays large, Sec. 4.2), and t
 of the data (how many distinct values a mode takes, how skewed it is, and how often it
 changes between neighbouring nonzeros of the input, which sets the bucket sizes of
 Alg. 2).
+
+Candidates (the schedules the selector chooses between; every one gives the same output):
+  0  MINIMAL (Alg. 3), bucketed groups run as one global sort where that is cheaper
+  1  MINIMAL with every bucketed group kept as bucket sorts        (valid when it differs from 0)
+  2  Top-K-sadilla with K = 1 (Sec. 3.6)                            (valid when K <= r - 2)
+  3  Top-K-sadilla with K = 2                                       (valid when K <= r - 2)
+  4  Top-K-sadilla with K = 3                                       (valid when K <= r - 2)
+  5  full LSD radix sort over all modes                             (valid when r >= 2)
+(K = r - 1 plans exactly what MINIMAL plans, so it is not a candidate of its own.)
 
 Sample.  With N nonzeros and S = min(N, 16384), the sampled positions are
 j_k = floor(k N / S), k = 0..S-1.  A sampled pair is (j_k, j_k + 1) when j_k + 1 < N.
@@ -16,30 +25,36 @@ Per mode m, three exact integer counts over the sample:
             the coordinate as a 64-bit integer (Steele, Lea and Flood, OOPSLA 2014);
   top_m     the largest count of one bucket ((h(x) >> 16) mod 1024) over the sample;
   change_m  sampled pairs whose coordinates in mode m differ.
-For a set of modes P: change_P = sampled pairs that differ in at least one mode of P.
+For a set of modes Q: change_Q = sampled pairs that differ in at least one mode of Q.  The
+sets: Q0 = the kept prefix of the minimal plan's first bucketed call (empty when it has none),
+Q1, Q2, Q3 = (sigma_1..sigma_K) for K = 1, 2, 3 (empty when K > r - 2).
 
 Distinct values are estimated by linear counting (Whang, Vander-Zanden and Taylor, ACM TODS
 1990): D = -M ln(zero / M) with M = 65536 (D = M ln M when no bit is zero).
 
+Plan terms of a candidate: its groups (consecutive partial sorts that keep the same prefix,
+as the library runs them), with modes of extent 1 dropped from the keys; a bucketed group is
+run as one global sort on (prefix, keys) when its key is wider than 52 bits, or (candidate 0
+and the Top-K candidates) when every nonzero packs into 64 bits, the flattened key is at most
+64 bits and it needs at most two digit passes more than the key alone.  A key of B bits is
+cut into 64-bit sub-keys and each into ceil(b / 8) digit passes.
+  gp  digit passes of the global groups;   sb  key bits of the bucketed groups.
+
 Feature vector (bits(n) = ceil(log2 n), 0 for n = 1; slot i is mode sigma_{i+1}; slots past
-the order are zero; K = min(2, r - 2) as for the Top-K schedule):
+the order are zero):
   0           log2(N) / 32
   1           r / 8
   2 + 4i      bits(n_sigma_i) / 32                        (i = 0..4)
   3 + 4i      log2(1 + D_sigma_i) / 24
   4 + 4i      change_sigma_i / pairs
   5 + 4i      top_sigma_i / S
-  22, 23      minimal plan (Alg. 3): plain calls / 8, bucketed calls / 8
-  24, 25      minimal plan: key bits of plain calls / 64, of bucketed calls / 64
-  26, 27      Top-K plan: key bits of plain calls / 64; key bits of bucketed calls plus the
-              bits of sigma_{K+1..r} when K > 0 (the per-bucket complete sort) / 64
-  28          full LSD plan: key bits of all modes / 64
-  29          change_P / pairs for P = the prefix of the minimal plan's first bucketed call
-              (0 when it has none)
-  30          change_P / pairs for P = (sigma_1..sigma_K) (0 when K = 0)
-  31          log2(1 + feature29 * N) / 32
+  22, 23      coordinate bytes / 8, value bytes / 8
+  24 + 2c     candidate c: gp / 16                         (c = 0..5; 0 when not valid)
+  25 + 2c     candidate c: sb / 64
+  36 + q      change_Qq / pairs                            (q = 0..3; 0 for an empty set)
 Parity: the counts are pinned by brute-force recounting in the tests and by closed forms
-(constant modes, all-distinct modes); the plan terms by the planner's own pins.
+(constant modes, all-distinct modes); the plan terms by the planner's own pins and by hand
+on small cases; the whole vector by a hand-derived golden example.
 """
 import math
 
@@ -47,11 +62,13 @@ import numpy as np
 
 from . import planner
 
-NFEAT = 32
+NFEAT = 40
+NCAND = 6
 SAMPLE = 16384
 BITMAP_BITS = 1 << 16
 BUCKETS = 1024
 SLOTS = 5
+RADIX = 8
 MASK64 = (1 << 64) - 1
 
 
@@ -109,32 +126,117 @@ def linear_count(zero):
     return M * math.log(M) if zero == 0 else -M * math.log(zero / M)
 
 
+def _passes(key_bits):
+    """Digit passes of a key: 64-bit sub-keys, each cut into ceil(b / 8) digits."""
+    d, left = 0, key_bits
+    while left > 0:
+        b = min(64, left)
+        d += -(-b // RADIX)
+        left -= b
+    return d
+
+
+def _groups(calls):
+    """Consecutive calls with the same kept prefix -> (prefix, keys most significant first)."""
+    out = []
+    for pre, m in calls:
+        if out and out[-1][0] == tuple(pre):
+            out[-1][1].insert(0, m)
+        else:
+            out.append((tuple(pre), [m]))
+    return out
+
+
+def _run_groups(groups, bits, keep_buckets):
+    """(global digit passes, bucketed key bits) of groups as the library runs them."""
+    total = sum(bits)
+    gp = sb = 0
+    for pre, keys in groups:
+        keys = [m for m in keys if bits[m] > 0]
+        if not keys:
+            continue
+        kb = sum(bits[m] for m in keys)
+        if not pre:
+            gp += _passes(kb)
+            continue
+        pb = sum(bits[m] for m in pre)
+        flat = kb > 52 or (not keep_buckets and total <= 64 and pb + kb <= 64 and
+                           -(-(pb + kb) // RADIX) <= -(-kb // RADIX) + 2)
+        if flat:
+            gp += _passes(pb + kb)
+        else:
+            sb += kb
+    return gp, sb
+
+
+def candidate_groups(tau_in, sigma, c):
+    """Groups of candidate c (None when the candidate is not valid for this request)."""
+    r = len(sigma)
+    if c in (0, 1):
+        return _groups(planner.plan(tau_in, sigma))
+    if c in (2, 3, 4):
+        K = c - 1
+        if K > r - 2:
+            return None
+        calls, _ = planner.topk_plan(tau_in, sigma, K)
+        g = _groups(calls)
+        pos = {m: i for i, m in enumerate(tau_in)}
+        q = r - 1
+        while q - 1 >= K and pos[sigma[q - 1]] < pos[sigma[q]]:
+            q -= 1
+        tail = list(sigma[K:q])
+        if tail:
+            g.append((tuple(sigma[:K]), tail))
+        return g
+    if c == 5:
+        return [((), list(sigma))] if r >= 2 else None
+    raise ValueError(c)
+
+
 def plan_terms(extents, tau_in, sigma):
-    """Call and key-bit counts of the three schedules, and the two bucket prefixes."""
+    """Per candidate (gp, sb) or None, and the four mode sets Q0..Q3."""
     r = len(sigma)
     bits = [bits_for_extent(n) for n in extents]
+    terms = []
+    for c in range(NCAND):
+        g = candidate_groups(tau_in, sigma, c)
+        terms.append(None if g is None else _run_groups(g, bits, keep_buckets=(c == 1)))
+    if _same_execution(tau_in, sigma, bits):
+        terms[1] = None
     s1 = planner.plan(tau_in, sigma)
-    K = max(0, min(2, r - 2))
-    s2, _ = planner.topk_plan(tau_in, sigma, K)
-    plain1 = [m for pre, m in s1 if not pre]
-    buck1 = [(pre, m) for pre, m in s1 if pre]
-    plain2 = [m for pre, m in s2 if not pre]
-    buck2 = [m for pre, m in s2 if pre]
-    tail2 = sum(bits[m] for m in sigma[K:]) if K > 0 else 0
-    return dict(
-        s1_plain_calls=len(plain1), s1_bucket_calls=len(buck1),
-        s1_plain_bits=sum(bits[m] for m in plain1), s1_bucket_bits=sum(bits[m] for _, m in buck1),
-        s2_plain_bits=sum(bits[m] for m in plain2), s2_bucket_bits=sum(bits[m] for m in buck2) + tail2,
-        s3_bits=sum(bits), prefix1=tuple(buck1[0][0]) if buck1 else (), prefix2=tuple(sigma[:K]))
+    buck = [pre for pre, _ in s1 if pre]
+    Q = [tuple(buck[0]) if buck else ()]
+    for K in (1, 2, 3):
+        Q.append(tuple(sigma[:K]) if K <= r - 2 else ())
+    return terms, Q
 
 
-def features(crd, extents, tau_in, sigma):
-    """The 32 features (float64) of transposing (crd, sorted under tau_in) to sigma."""
+def _same_execution(tau_in, sigma, bits):
+    """Candidate 1 runs differently from candidate 0 exactly when some bucketed group of the
+    minimal plan is flattened without the flag (and kept with it)."""
+    total = sum(bits)
+    for pre, keys in _groups(planner.plan(tau_in, sigma)):
+        keys = [m for m in keys if bits[m] > 0]
+        if not pre or not keys:
+            continue
+        kb = sum(bits[m] for m in keys)
+        pb = sum(bits[m] for m in pre)
+        if kb <= 52 and total <= 64 and pb + kb <= 64 and -(-(pb + kb) // RADIX) <= -(-kb // RADIX) + 2:
+            return False
+    return True
+
+
+def valid_candidates(extents, tau_in, sigma):
+    terms, _ = plan_terms(extents, tau_in, sigma)
+    return [t is not None for t in terms]
+
+
+def features(crd, extents, tau_in, sigma, crd_bytes=4, val_bytes=8):
+    """The 40 features (float64) of transposing (crd, sorted under tau_in) to sigma."""
     r = len(sigma)
     n = len(crd[0])
-    pt = plan_terms(extents, tau_in, sigma)
-    masks = [pt["prefix1"], pt["prefix2"]]
-    per_mode, mch, S, pairs = counts(crd, masks)
+    terms, Q = plan_terms(extents, tau_in, sigma)
+    per_mode, mch, S, pairs = counts(crd, Q)
     f = np.zeros(NFEAT)
     f[0] = math.log2(n) / 32 if n > 0 else 0.0
     f[1] = r / 8
@@ -145,14 +247,12 @@ def features(crd, extents, tau_in, sigma):
         f[3 + 4 * i] = math.log2(1.0 + linear_count(zero)) / 24 if S else 0.0
         f[4 + 4 * i] = change / pairs if pairs else 0.0
         f[5 + 4 * i] = top / S if S else 0.0
-    f[22] = pt["s1_plain_calls"] / 8
-    f[23] = pt["s1_bucket_calls"] / 8
-    f[24] = pt["s1_plain_bits"] / 64
-    f[25] = pt["s1_bucket_bits"] / 64
-    f[26] = pt["s2_plain_bits"] / 64
-    f[27] = pt["s2_bucket_bits"] / 64
-    f[28] = pt["s3_bits"] / 64
-    f[29] = mch[0] / pairs if (pairs and pt["prefix1"]) else 0.0
-    f[30] = mch[1] / pairs if (pairs and pt["prefix2"]) else 0.0
-    f[31] = math.log2(1.0 + f[29] * n) / 32
+    f[22] = crd_bytes / 8
+    f[23] = val_bytes / 8
+    for c, t in enumerate(terms):
+        if t is not None:
+            f[24 + 2 * c] = t[0] / 16
+            f[25 + 2 * c] = t[1] / 64
+    for q in range(4):
+        f[36 + q] = mch[q] / pairs if (pairs and Q[q]) else 0.0
     return f

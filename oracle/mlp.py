@@ -3,13 +3,14 @@
 The paper observes that the minimal number of passes is not always the fastest plan and
 proposes minimising a model of the true cost instead (Sec. 5; Sec. 4.2 on the effect of
 large extents).  The selector realises that model as a small fully connected
-network 32 -> 64 -> 64 -> 3 with ReLU after the two hidden layers, predicting the base-2
-logarithm of the run time (ms) of each of three schedules; it is trained by minimising the
-mean squared error with Adam (Kingma and Ba, "Adam: A Method for Stochastic Optimization",
-ICLR 2015, Algorithm 1).
+network 40 -> 64 -> 64 -> 6 with ReLU after the two hidden layers, predicting the base-2
+logarithm of the run time (ms) of each of six candidate schedules; it is trained by
+minimising the mean squared error (a target that is not a number -- a candidate that does not
+exist for that request -- contributes zero) with Adam (Kingma and Ba, "Adam: A Method for
+Stochastic Optimization", ICLR 2015, Algorithm 1).
 
-Parameter vector layout (float, 6467 entries): W1 (64 x 32, row-major: W1[o, i]), b1 (64),
-W2 (64 x 64), b2 (64), W3 (3 x 64), b3 (3).
+Parameter vector layout (float, 7174 entries): W1 (64 x 40, row-major: W1[o, i]), b1 (64),
+W2 (64 x 64), b2 (64), W3 (6 x 64), b3 (6).
 
 Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom
 number generators", OOPSLA 2014; the 64-bit variant published by Vigna), so that the
@@ -20,7 +21,7 @@ the last bias; a zero-loss dataset leaves Adam still), Adam's first-step propert
 """
 import numpy as np
 
-SIZES = (32, 64, 64, 3)
+SIZES = (40, 64, 64, 6)
 MASK64 = (1 << 64) - 1
 
 
@@ -94,20 +95,26 @@ def forward(theta, X):
     return h1, h2, y
 
 
+def _errors(y, T):
+    """y - T where the target is a number, 0 where it is not."""
+    T = np.asarray(T, dtype=np.float64)
+    return np.where(np.isnan(T), 0.0, y - np.where(np.isnan(T), 0.0, T))
+
+
 def loss(theta, X, T):
-    """Mean over rows and outputs of the squared error."""
+    """Mean over rows and outputs of the squared error (NaN targets contribute zero)."""
     _, _, y = forward(theta, X)
-    return float(np.mean((y - np.asarray(T, dtype=np.float64)) ** 2))
+    return float(np.mean(_errors(y, T) ** 2))
 
 
 def backward(theta, X, T):
     """(loss, gradient of the loss with respect to theta), by the chain rule layer by layer."""
     p = unpack(theta)
     X = np.asarray(X, dtype=np.float64)
-    T = np.asarray(T, dtype=np.float64)
     h1, h2, y = forward(theta, X)
     n = X.shape[0]
-    d3 = 2.0 * (y - T) / (n * SIZES[3])          # dL/dy
+    e = _errors(y, T)
+    d3 = 2.0 * e / (n * SIZES[3])                # dL/dy
     g = {"W3": d3.T @ h2, "b3": d3.sum(axis=0)}
     d2 = (d3 @ p["W3"]) * (h2 > 0)               # dL/d(pre-activation of layer 2)
     g["W2"] = d2.T @ h1
@@ -115,7 +122,7 @@ def backward(theta, X, T):
     d1 = (d2 @ p["W2"]) * (h1 > 0)
     g["W1"] = d1.T @ X
     g["b1"] = d1.sum(axis=0)
-    return float(np.mean((y - T) ** 2)), pack(g)
+    return float(np.mean(e ** 2)), pack(g)
 
 
 def adam_step(theta, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
@@ -141,7 +148,7 @@ def train(theta, X, T, epochs, batch, lr, seed, beta1=0.9, beta2=0.999, eps=1e-8
     `batch` rows (the last one may be shorter).  Returns (theta, loss of the last batch)."""
     theta = np.array(theta, dtype=np.float64)
     X = np.asarray(X, dtype=np.float64)
-    T = np.asarray(T, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)  # NaN entries: no target
     m = np.zeros_like(theta)
     v = np.zeros_like(theta)
     rng = SplitMix64(seed)

@@ -224,10 +224,10 @@ struct Bufs {
 
 // ---- launch timing (qsd_profile_*)
 enum Kind { kZero, kCopy, kValidate, kHist, kDigit, kBoundary, kClassify, kSmall, kHistSeg, kDigitSeg, kCsf,
-            kHistBatch, kSmallBatch, kDigitBatch, kNumKinds };
+            kHistBatch, kSmallBatch, kDigitBatch, kCsfExpand, kNumKinds };
 const char* kKindName[kNumKinds] = {"zero", "copy", "validate", "hist", "digit", "boundary",
                                     "classify", "small", "hist_seg", "digit_seg", "csf",
-                                    "hist_batch", "small_batch", "digit_batch"};
+                                    "hist_batch", "small_batch", "digit_batch", "csf_expand"};
 struct ProfRec {
     int kind;
     hipEvent_t a, b;
@@ -312,7 +312,8 @@ qsd_status qsd_plan(const qsd_desc* desc, qsd_sched_t sched, qsd_plan_t* out) {
     int passes = 0;
     for (const auto& g : p.groups)
         for (const auto& s : g.subs) passes += (int)s.passes.size();
-    if (passes > kCtlWords - kCtlPassCnt) {  // one tile counter per pass in the control block
+    // tile counters of every pass in the control block (its last 8 words serve the CSF expansion)
+    if (passes * kPassCounters > kCtlWords - kCtlPassCnt - 8) {
         delete q;
         return QSD_ERR_UNSUPPORTED;
     }
@@ -503,7 +504,7 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
                     da.hist = hist + (size_t)i * kBins;
                     da.status = S[q % 2];
                     da.status_next = (i + 1 < np) ? S[(q + 1) % 2] : nullptr;
-                    da.tile_counter = ctl + kCtlPassCnt + q;
+                    da.tile_counter = ctl + kCtlPassCnt + kPassCounters * q;
                     da.err = ctl + kCtlErr;
                     QSD_CK(timed(kDigit, bytes, stream, [&] {
                         return launch_digit(da, r_launch, cb_launch, p.val_bytes, plan->items, stream);
@@ -635,7 +636,7 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
             da.hist = seg_hist + (size_t)i * kBins;
             da.status = S[q % 2];
             da.status_next = (i + 1 < np) ? S[(q + 1) % 2] : nullptr;
-            da.tile_counter = ctl + kCtlPassCnt + q;
+            da.tile_counter = ctl + kCtlPassCnt + kPassCounters * q;
             da.large_ctl = large_ctl;
             da.large = large;
             da.tile_map = tile_map;
@@ -711,7 +712,7 @@ qsd_status qsd_device_status(void* ws, hipStream_t stream, uint32_t* code) {
 qsd_status qsd_csf_workspace(qsd_plan_t plan, size_t* bytes) {
     if (!plan || !bytes) return QSD_ERR_NULL;
     const uint64_t N = (uint64_t)std::max<int64_t>(plan->p.nnz, 1);
-    *bytes = up(kCtlWords * 4) + up(cdiv(N, kBlock * 8) * 8 * 4);
+    *bytes = up(kCtlWords * 4) + up(cdiv(N, kCsfTile) * 8 * 4);
     return QSD_OK;
 }
 
@@ -730,7 +731,7 @@ qsd_status qsd_pack_csf(qsd_plan_t plan, int64_t nnz, const void* const* sorted_
     char* W = (char*)ws;
     uint32_t* ctl = (uint32_t*)W;
     uint32_t* st = (uint32_t*)(W + up(kCtlWords * 4));
-    const uint64_t tiles = cdiv(std::max<uint32_t>(n, 1), kBlock * 8);
+    const uint64_t tiles = cdiv(std::max<uint32_t>(n, 1), kCsfTile);
     ZeroArgs z{};
     z.ctl = ctl;
     z.ptr[1] = st;
@@ -766,6 +767,105 @@ qsd_status qsd_pack_csf(qsd_plan_t plan, int64_t nnz, const void* const* sorted_
     ca.err = ctl + kCtlErr;
     if (timed(kCsf, 0, stream, [&] { return launch_csf(ca, p.crd_bytes, stream); }) != hipSuccess) return QSD_ERR_HIP;
     return QSD_OK;
+}
+
+// ---- CSF -> CSF: expansion to coordinates, the plan's transposition, the pack
+namespace {
+struct CsfTLayout {
+    size_t plan_ws = 0, csf_ws = 0, status = 0, flags = 0, coo_in = 0, coo_out = 0, total = 0;
+    uint64_t tiles = 0;
+};
+CsfTLayout csf_t_layout(qsd_plan_t plan) {
+    const PlanData& p = plan->p;
+    const uint64_t N = (uint64_t)std::max<int64_t>(p.nnz, 1);
+    CsfTLayout L;
+    size_t at = 0;
+    L.plan_ws = at;  // first: its control block is the call's (status bits, counters)
+    at = up(at + plan->L.total);
+    size_t cw = 0;
+    qsd_csf_workspace(plan, &cw);
+    L.csf_ws = at;
+    at = up(at + cw);
+    L.tiles = cdiv(N, kBoundTile);
+    L.status = at;
+    at = up(at + (size_t)std::max(p.r - 1, 1) * L.tiles * 4);
+    L.flags = at;
+    at = up(at + (size_t)std::max(p.r - 1, 1) * up(N));
+    L.coo_in = at;
+    at = up(at + (size_t)p.r * up(N * p.crd_bytes));
+    L.coo_out = at;
+    at = up(at + (size_t)p.r * up(N * p.crd_bytes));
+    L.total = at;
+    return L;
+}
+}  // namespace
+
+qsd_status qsd_csf_transpose_workspace(qsd_plan_t plan, size_t* bytes) {
+    if (!plan || !bytes) return QSD_ERR_NULL;
+    *bytes = csf_t_layout(plan).total;
+    return QSD_OK;
+}
+
+qsd_status qsd_csf_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_pos, const void* const* in_crd,
+                             const void* in_val, void* const* out_pos, void* const* out_crd, void* out_val,
+                             int64_t* fiber_counts, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!plan || !in_pos || !in_crd || !out_pos || !out_crd || !fiber_counts) return QSD_ERR_NULL;
+    const PlanData& p = plan->p;
+    if (nnz < 0 || nnz > p.nnz) return QSD_ERR_TOO_LARGE;
+    const CsfTLayout L = csf_t_layout(plan);
+    if (!ws || ws_bytes < L.total) return QSD_ERR_WORKSPACE;
+    for (int m = 0; m < p.r; ++m)
+        if (!in_pos[m] || !in_crd[m] || !out_pos[m] || !out_crd[m]) return QSD_ERR_NULL;
+    if (nnz > 0 && (!in_val || !out_val)) return QSD_ERR_NULL;
+    char* W = (char*)ws;
+    const uint32_t n = (uint32_t)nnz;
+    const uint64_t N = (uint64_t)std::max<int64_t>(p.nnz, 1);
+    const void* coo_in[kMaxR];
+    void* coo_out[kMaxR];
+    for (int m = 0; m < p.r; ++m) coo_out[m] = W + L.coo_out + (size_t)m * up(N * p.crd_bytes);
+    if (n > 0) {
+        uint32_t* ctl = (uint32_t*)(W + L.plan_ws);
+        ZeroArgs z{};
+        z.ctl = ctl;
+        z.ptr[0] = (uint32_t*)(W + L.status);
+        z.words[0] = (uint64_t)std::max(p.r - 1, 1) * L.tiles;
+        z.ptr[1] = (uint32_t*)(W + L.flags);
+        z.words[1] = (uint64_t)std::max(p.r - 1, 1) * up(N) / 4;
+        if (timed(kZero, 0, stream, [&] { return launch_zero(z, stream); }) != hipSuccess) return QSD_ERR_HIP;
+        // levels 1 .. r-1 of the input tree (level d stores mode in_order[d-1]) expand into
+        // coordinate arrays; the leaf level is the last mode's coordinate array already
+        for (int d = 1; d < p.r; ++d) {
+            CsfExpandArgs a{};
+            for (int e = 0; e < p.r; ++e) {
+                a.pos[e] = in_pos[e];
+                a.crd[e] = in_crd[e];
+            }
+            a.r = p.r;
+            a.level = d;
+            a.n = n;
+            a.flags = (uint8_t*)(W + L.flags) + (size_t)(d - 1) * up(N);
+            a.status = (uint32_t*)(W + L.status) + (size_t)(d - 1) * L.tiles;
+            a.tile_counter = ctl + kCtlWords - 1 - d;
+            a.err = ctl + kCtlErr;
+            void* out = W + L.coo_in + (size_t)p.in_order[d - 1] * up(N * p.crd_bytes);
+            a.out = out;
+            coo_in[p.in_order[d - 1]] = out;
+            if (timed(kCsfExpand, (double)n * (1.0 + 2.0 * p.crd_bytes), stream,
+                      [&] {
+                          hipError_t e = launch_csf_mark(a, p.crd_bytes, stream);
+                          return e == hipSuccess ? launch_csf_expand(a, p.crd_bytes, stream) : e;
+                      }) != hipSuccess)
+                return QSD_ERR_HIP;
+        }
+        coo_in[p.in_order[p.r - 1]] = in_crd[p.r - 1];
+        const qsd_status st = qsd_transpose(plan, nnz, coo_in, in_val, coo_out, out_val, W + L.plan_ws,
+                                            plan->L.total, stream);
+        if (st != QSD_OK) return st;
+    }
+    size_t cw = 0;
+    qsd_csf_workspace(plan, &cw);
+    return qsd_pack_csf(plan, nnz, (const void* const*)coo_out, out_pos, out_crd, fiber_counts, W + L.csf_ws, cw,
+                        stream);
 }
 
 }  // extern "C"
@@ -1219,7 +1319,7 @@ qsd_status qsd_batch_transpose(qsd_batch_t b, void* ws, size_t ws_bytes, hipStre
             da.batch = (const BatchPass*)(T + b->tab_pass) + (size_t)p * nl;
             da.status = S[p % 2];
             da.status_next = (p + 1 < b->maxD) ? S[(p + 1) % 2] : nullptr;
-            da.tile_counter = ctl + kCtlPassCnt + l;
+            da.tile_counter = ctl + kCtlPassCnt + kPassCounters * l;
             da.err = ctl + kCtlErr;
             const int r_launch = kind == kKindWords ? 1 : b->rmax;
             const int cb_launch = kind == kKindWords ? 8 : b->crd_bytes;

@@ -24,8 +24,9 @@ enum CtlSlot {
     kCtlLarge = 4,      // uint64 at words 4-5: (large segments << 32) | large tiles
     kCtlBoundCnt = 8,   // tile counter of the boundary scan
     kCtlMagic = 9,      // kCtlStickyMagic once kCtlErr holds accumulated status bits
-    kCtlPassCnt = 16,   // tile counters, one per digit pass launch
+    kCtlPassCnt = 16,   // tile counters, kPassCounters per digit pass launch
 };
+constexpr int kPassCounters = 8;  // a global pass's tile queues
 // The status bits of kCtlErr accumulate over calls (the library clears them when the host reads
 // them).  A fresh workspace holds arbitrary bytes: the first call that finds the magic word
 // missing clears the bits and writes it.
@@ -96,7 +97,7 @@ struct DigitArgs {
     const uint32_t* hist;       // this pass's digit histogram (segment mode: of segment 0)
     uint32_t* status;           // look-back words of this pass, kBins per tile
     uint32_t* status_next;      // zeroed for the next pass (may be null)
-    uint32_t* tile_counter;
+    uint32_t* tile_counter;     // global and batch modes: kPassCounters queues; segment mode: one
     const uint64_t* large_ctl;  // segment mode
     const SegRec* large;        // segment mode
     const uint32_t* tile_map;   // segment mode: large segment of every tile; batch mode: four
@@ -231,6 +232,8 @@ struct ValidateArgs {
     uint32_t* flags;            // bit 0: out of range, bit 1: unsorted
 };
 
+constexpr int kCsfTile = 2048;     // records per tile of the CSF pack
+
 struct CsfArgs {
     const void* crd[8];         // sorted coordinates, original mode order
     int32_t r;
@@ -244,7 +247,28 @@ struct CsfArgs {
     uint32_t* err;
 };
 
+// Expansion of a CSF tensor (the layout qsd_pack_csf writes) to coordinate arrays, level by
+// level.  Level d (1-based) holds F_d fibers; pos[d-1] has F_{d-1} + 1 entries (the children
+// of level-(d-1) fiber p are level-d fibers pos[d-1][p] .. pos[d-1][p+1]-1), crd[d-1] has F_d.
+// F_0 = 1 and F_d = pos[d-1][F_{d-1}], so every count is read from the arrays themselves.
+struct CsfExpandArgs {
+    const void* pos[8];
+    const void* crd[8];
+    int32_t r;
+    int32_t level;              // d: the level this launch expands (1 <= d < r)
+    uint32_t n;                 // leaves
+    uint8_t* flags;             // n bytes: 1 where a leaf is the first leaf of a level-d fiber
+    uint32_t* status;           // one word per tile of kBoundTile leaves, zeroed beforehand
+    uint32_t* tile_counter;
+    void* out;                  // the level's coordinate of every leaf
+    uint32_t* err;
+};
+
 hipError_t launch_zero(const ZeroArgs& a, hipStream_t s);
+// flags[first leaf of every level-d fiber] = 1 (flags zeroed beforehand)
+hipError_t launch_csf_mark(const CsfExpandArgs& a, int crd_bytes, hipStream_t s);
+// out[j] = crd[d-1][number of flags at or before j, minus 1]
+hipError_t launch_csf_expand(const CsfExpandArgs& a, int crd_bytes, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_hist(const HistArgs& a, int r, int crd_bytes, int grid, hipStream_t s);
 hipError_t launch_digit(const DigitArgs& a, int r, int crd_bytes, int val_bytes, int items, hipStream_t s);

@@ -126,10 +126,28 @@ __global__ void __launch_bounds__(256) k_zero(ZeroArgs a) {
     }
 }
 
-__global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+// Streaming copy: four independent 16-byte loads per thread in flight, then four stores, with
+// the non-temporal cache policy (the data is touched once); the bytes past the last whole
+// 16-byte word one at a time.  16 workgroups per CU: 5.8 TB/s (read + write) on 1.6 GB.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
                                               uint64_t n16, const uint8_t* __restrict__ sb,
                                               uint8_t* __restrict__ db, uint64_t bytes) {
-    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n16; i += gridDim.x * 256ull) dst[i] = src[i];
+    constexpr int U = 4;
+    const uint64_t stride = (uint64_t)gridDim.x * 256 * U;
+    for (uint64_t base = blockIdx.x * 256ull * U + threadIdx.x; base < n16; base += stride) {
+        u32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = base + u * 256ull;
+            if (i < n16) v[u] = __builtin_nontemporal_load(&src[i]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = base + u * 256ull;
+            if (i < n16) __builtin_nontemporal_store(v[u], &dst[i]);
+        }
+    }
     for (uint64_t i = n16 * 16 + blockIdx.x * 256ull + threadIdx.x; i < bytes; i += gridDim.x * 256ull)
         db[i] = sb[i];
 }
@@ -244,6 +262,15 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
 // ------------------------------------------------------------------------------ digit pass
 
 constexpr int kLookWin = 8;  // status words read per look-back round trip
+// Global passes hand tiles out from 8 queues (one per XCD when workgroups are dispatched to the
+// 8 XCDs round-robin), each in chunks of kTileChunk consecutive tiles, so that the partial
+// cache lines where neighbouring tiles' digit runs meet are mostly written through one L2
+// (plain workload: 891 -> 810 us per pass; chunks of 4, 16 and 32 tiles: 833, 812, 834 us).
+// Below kQueueMinTiles tiles a launch uses one queue: with few tiles, chunks of 8 leave most
+// queues (and their workgroups) without work.
+constexpr uint32_t kTileQueues = 8;
+constexpr uint32_t kTileChunk = 8;
+constexpr uint32_t kQueueMinTiles = 2048;
 
 // Decoupled look-back done by one whole wave for one counter: lane l reads the status of
 // tile j - l, so 64 predecessors are inspected per round trip.  Statuses are at
@@ -406,7 +433,14 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
 
     for (;;) {
         if (tid == 0) {
-            const uint32_t lt = atomicAdd(a.tile_counter, 1u);
+            // global and batch modes: queue q (of G) hands out chunks q, q + G, q + 2G, ... of
+            // kTileChunk consecutive (launch) tiles.  Every queue has a workgroup (G <= grid),
+            // each queue's tiles go out in increasing order, and a tile waits only for lower
+            // tiles, so the lowest unfinished tile always has a running workgroup or a free one
+            // that will take it.
+            const uint32_t G = (MODE != 1 && a.ntiles >= kQueueMinTiles) ? min(kTileQueues, gridDim.x) : 1u;
+            const uint32_t qi = blockIdx.x % G;
+            const uint32_t lt = atomicAdd(a.tile_counter + qi, 1u);
             uint32_t t = lt, ntiles = a.ntiles, start = 0, len = 0, base = 0, k = 0, lowest = 0;
             bool live = false;
             if (MODE == 1) {
@@ -421,10 +455,11 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                     live = true;
                 }
             } else if (MODE == 2) {
-                if (lt < ntiles) {
+                const uint32_t lq = ((lt / kTileChunk) * G + qi) * kTileChunk + lt % kTileChunk;
+                if (lq < ntiles) {
                     // one load: stable tile id (the look-back words are indexed by it), tensor,
                     // first record and record count of the launch tile
-                    const uint4 g = reinterpret_cast<const uint4*>(a.tile_map)[lt];
+                    const uint4 g = reinterpret_cast<const uint4*>(a.tile_map)[lq];
                     t = g.x;
                     k = g.y;
                     start = g.z;
@@ -432,10 +467,13 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                     lowest = t - start / TILE;  // the tensor's first tile
                     live = true;
                 }
-            } else if (lt < ntiles) {
-                start = lt * TILE;
-                len = min((uint32_t)TILE, a.n - start);
-                live = true;
+            } else {
+                t = ((lt / kTileChunk) * G + qi) * kTileChunk + lt % kTileChunk;
+                if (t < ntiles) {
+                    start = t * TILE;
+                    len = min((uint32_t)TILE, a.n - start);
+                    live = true;
+                }
             }
             s_geo[0] = live ? t : 0xFFFFFFFFu;
             s_geo[1] = start;
@@ -673,6 +711,87 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
 template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_digit3(DigitArgs a) {
     digit_body<R, CT, VT, ITEMS, MODE, PK>(a);
+}
+
+// ------------------------------------------------------------------------------ CSF expansion
+
+// F_d of a CSF tensor: F_0 = 1 and F_e = pos[e-1][F_{e-1}].
+template <typename PT>
+__device__ __forceinline__ uint64_t csf_fibers(const CsfExpandArgs& a, int d) {
+    uint64_t f = 1;
+    for (int e = 1; e <= d; ++e) f = (uint64_t)((const PT*)a.pos[e - 1])[f];
+    return f;
+}
+
+// Every level-d fiber marks its first leaf: following the first child down from level d to the
+// leaves, x <- pos[e][x] for e = d .. r-1.  Leaf indices are clamped into [0, n) so that a
+// malformed tensor cannot write outside the flags.
+template <typename PT>
+__global__ void __launch_bounds__(256) k_csf_mark(CsfExpandArgs a) {
+    uint64_t Fe[9];  // fiber counts of every level, each index below clamped to its array
+    Fe[0] = 1;
+    for (int e = 1; e <= a.r; ++e) Fe[e] = (uint64_t)((const PT*)a.pos[e - 1])[Fe[e - 1]];
+    const uint64_t F = Fe[a.level];
+    for (uint64_t f = blockIdx.x * (uint64_t)kBlock + threadIdx.x; f < F; f += gridDim.x * (uint64_t)kBlock) {
+        uint64_t x = f;
+        for (int e = a.level; e < a.r; ++e) x = (uint64_t)((const PT*)a.pos[e])[min(x, Fe[e])];
+        if (x < a.n) a.flags[x] = 1;
+    }
+}
+
+// The level-d coordinate of every leaf: its level-d ancestor is the number of fibers whose first
+// leaf is at or before it, minus one (an inclusive count of the flags, tiles chained by a
+// one-word decoupled look-back), and the coordinate is that fiber's entry of crd[d-1].
+template <typename CT>
+__global__ void __launch_bounds__(256) k_csf_expand(CsfExpandArgs a) {
+    constexpr int ITEMS = kBoundTile / kBlock;
+    __shared__ uint32_t s_wsum[kWaves];
+    __shared__ uint32_t s_geo[2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) s_geo[0] = atomicAdd(a.tile_counter, 1u);
+    __syncthreads();
+    const uint32_t t = s_geo[0];
+    const uint32_t start = t * kBoundTile;
+    if (start >= a.n) return;
+    const uint32_t len = min((uint32_t)kBoundTile, a.n - start);
+    const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
+    uint64_t flags[ITEMS];
+    uint32_t wcount = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t off = wb + i * 64;
+        flags[i] = ballot(off < len && a.flags[start + off] != 0);
+        wcount += (uint32_t)__popcll(flags[i]);
+    }
+    if (lane == 0) s_wsum[wave] = wcount;
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += s_wsum[w];
+        uint32_t* st = a.status + t;
+        if (lane == 0) st_status(st, (t == 0 ? kFlagP : kFlagA) | tot);
+        const uint32_t excl = t == 0 ? 0u : wave_look_back(a.status, t, 1, 0, 0, a.err);
+        if (lane == 0) {
+            if (t != 0) st_status(st, kFlagP | (excl + tot));
+            s_geo[1] = excl;
+        }
+    }
+    __syncthreads();
+    uint32_t pos = s_geo[1];
+    for (int w = 0; w < wave; ++w) pos += s_wsum[w];
+    const CT* crd = (const CT*)a.crd[a.level - 1];
+    const uint64_t F = csf_fibers<CT>(a, a.level);
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint64_t f = flags[i];
+        const uint32_t off = wb + i * 64;
+        const uint32_t incl = pos + lanes_below(f) + (uint32_t)((f >> lane) & 1ull);  // flags at or before
+        if (off < len) {
+            const uint64_t anc = incl ? min((uint64_t)incl - 1, F ? F - 1 : 0) : 0;
+            ((CT*)a.out)[start + off] = crd[anc];
+        }
+        pos += (uint32_t)__popcll(f);
+    }
 }
 
 // ------------------------------------------------------------------------------ buckets
@@ -1348,132 +1467,123 @@ __global__ void __launch_bounds__(256) k_validate(ValidateArgs a) {
 // (r-1)-word look-back; level r is the identity.  Writes crd_d and pos_d.
 template <typename CT, typename PT>
 __global__ void __launch_bounds__(256) k_csf(CsfArgs a) {
-    constexpr int ITEMS = 8, TILE = kBlock * ITEMS;
+    constexpr int ITEMS = kCsfTile / kBlock, TILE = kCsfTile;
     __shared__ uint32_t s_wsum[8][kWaves];
     __shared__ uint32_t s_excl[8];
     __shared__ uint32_t s_t;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int L = a.r - 1;  // counted levels
-    if (tid == 0) s_t = atomicAdd(a.tile_counter, 1u);
-    __syncthreads();
-    const uint32_t t = s_t;
-    const uint32_t start = t * TILE;
-    if (start >= a.n) return;
-    const uint32_t len = min((uint32_t)TILE, a.n - start);
-    const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
-    // level of the first differing mode: records j with first-difference level <= d start
-    // a level-d fiber.  lev = 0 for the first record (every level starts).
-    uint8_t lev[ITEMS];
-    uint32_t wcnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // persistent: tiles in increasing order from one counter, so that every look-back ends
+    for (;;) {
+        if (tid == 0) s_t = atomicAdd(a.tile_counter, 1u);
+        __syncthreads();
+        const uint32_t t = s_t;
+        const uint32_t start = t * TILE;
+        if (start >= a.n) break;
+        const uint32_t len = min((uint32_t)TILE, a.n - start);
+        const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
+        // level of the first differing mode: records j with first-difference level <= d start
+        // a level-d fiber.  lev = 0 for the first record (every level starts).
+        uint8_t lev[ITEMS];
+        uint32_t wcnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t off = wb + i * 64;
-        // lev: first level whose mode differs from the previous record (r: none below r)
-        lev[i] = off < len ? (start + off == 0 ? 0 : (uint8_t)a.r) : 0xFF;
-    }
-    for (int d = L - 1; d >= 0; --d) {  // deepest level first, so the shallowest wins
-        const CT* p = (const CT*)a.crd[a.sigma[d]];
-        CT cur[ITEMS], prv[ITEMS];
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t off = wb + i * 64;
+            // lev: first level whose mode differs from the previous record (r: none below r)
+            lev[i] = off < len ? (start + off == 0 ? 0 : (uint8_t)a.r) : 0xFF;
+        }
+        for (int d = L - 1; d >= 0; --d) {  // deepest level first, so the shallowest wins
+            const CT* p = (const CT*)a.crd[a.sigma[d]];
+            CT cur[ITEMS], prv[ITEMS];
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t off = wb + i * 64;
+                const uint32_t e = start + off;
+                const bool ok = off < len && e > 0;
+                cur[i] = ok ? p[e] : CT(0);
+                prv[i] = ok ? p[e - 1] : CT(0);
+            }
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i)
+                if (lev[i] != 0xFF && lev[i] != 0 && cur[i] != prv[i]) lev[i] = (uint8_t)d;
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t off = wb + i * 64;
+            const int lv = lev[i];
+            for (int d = 0; d < L; ++d) wcnt[d] += (uint32_t)__popcll(ballot(off < len && lv <= d));
+        }
+        if (lane == 0)
+            for (int d = 0; d < L; ++d) s_wsum[d][wave] = wcnt[d];
+        __syncthreads();
+        // fiber numbers before this tile: one wave per level, 64 predecessors per round trip
+        for (int d = wave; d < L; d += kWaves) {
+            uint32_t tot = 0;
+            for (int w = 0; w < kWaves; ++w) tot += s_wsum[d][w];
+            uint32_t* st = a.status + (size_t)t * 8 + d;
+            uint32_t excl = 0;
+            if (t == 0) {
+                if (lane == 0) st_status(st, kFlagP | tot);
+            } else {
+                if (lane == 0) st_status(st, kFlagA | tot);
+                excl = wave_look_back(a.status, t, 8, (uint32_t)d, 0, a.err);
+                if (lane == 0) st_status(st, kFlagP | (excl + tot));
+            }
+            if (lane == 0) {
+                s_excl[d] = excl;
+                if (start + len == a.n) a.fiber_counts[d + 1] = excl + tot;
+            }
+        }
+        if (tid == 0 && start + len == a.n) {
+            a.fiber_counts[0] = 1;
+            a.fiber_counts[a.r] = a.n;
+        }
+        __syncthreads();
+        // running fiber number per level for this thread's records
+        uint32_t base[8];
+        for (int d = 0; d < L; ++d) {
+            uint32_t b = s_excl[d];
+            for (int w = 0; w < wave; ++w) b += s_wsum[d][w];
+            base[d] = b;
+        }
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t off = wb + i * 64;
             const uint32_t e = start + off;
-            const bool ok = off < len && e > 0;
-            cur[i] = ok ? p[e] : CT(0);
-            prv[i] = ok ? p[e - 1] : CT(0);
-        }
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i)
-            if (lev[i] != 0xFF && lev[i] != 0 && cur[i] != prv[i]) lev[i] = (uint8_t)d;
-    }
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t off = wb + i * 64;
-        const int lv = lev[i];
-        for (int d = 0; d < L; ++d) wcnt[d] += (uint32_t)__popcll(ballot(off < len && lv <= d));
-    }
-    if (lane == 0)
-        for (int d = 0; d < L; ++d) s_wsum[d][wave] = wcnt[d];
-    __syncthreads();
-    if (tid < L) {
-        const int d = tid;
-        uint32_t tot = 0;
-        for (int w = 0; w < kWaves; ++w) tot += s_wsum[d][w];
-        uint32_t* st = a.status + (size_t)t * 8 + d;
-        uint32_t excl = 0;
-        if (t == 0) {
-            st_status(st, kFlagP | tot);
-        } else {
-            st_status(st, kFlagA | tot);
-            uint32_t j = t - 1, spins = 0;
-            for (;;) {
-                const uint32_t w = ld_status(&a.status[(size_t)j * 8 + d]);
-                const uint32_t f = w & ~kCntMask;
-                if (f == 0) {
-                    if (++spins > kSpinLimit) {
-                        atomicOr(a.err, 1u);
-                        break;
+            const int lv = lev[i];
+            uint32_t fid[8];
+            for (int d = 0; d < L; ++d) {
+                const uint64_t m = ballot(off < len && lv <= d);
+                fid[d] = base[d] + lanes_below(m);  // fiber number if this record starts one
+                base[d] += (uint32_t)__popcll(m);
+            }
+            if (off < len) {
+                // level d (1-based) fiber starts here when lv <= d-1; leaves always start
+                for (int d = 1; d <= a.r; ++d) {
+                    const bool starts = (d == a.r) || (lv <= d - 1);
+                    if (!starts) continue;
+                    const uint32_t f = (d == a.r) ? e : fid[d - 1];
+                    ((CT*)a.out_crd[d - 1])[f] = ((const CT*)a.crd[a.sigma[d - 1]])[e];
+                    // a new parent at level d-1 (or the root for d = 1) records its first child
+                    if (d == 1) {
+                        if (e == 0) ((PT*)a.pos[0])[0] = 0;
+                    } else if (lv <= d - 2) {
+                        ((PT*)a.pos[d - 1])[fid[d - 2]] = (PT)f;
                     }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                excl += w & kCntMask;
-                if (f == kFlagP) break;
-                --j;
-            }
-            st_status(st, kFlagP | (excl + tot));
-        }
-        s_excl[d] = excl;
-        if (start + len == a.n) a.fiber_counts[d + 1] = excl + tot;
-    }
-    if (tid == 0 && start + len == a.n) {
-        a.fiber_counts[0] = 1;
-        a.fiber_counts[a.r] = a.n;
-    }
-    __syncthreads();
-    // running fiber number per level for this thread's records
-    uint32_t base[8];
-    for (int d = 0; d < L; ++d) {
-        uint32_t b = s_excl[d];
-        for (int w = 0; w < wave; ++w) b += s_wsum[d][w];
-        base[d] = b;
-    }
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t off = wb + i * 64;
-        const uint32_t e = start + off;
-        const int lv = lev[i];
-        uint32_t fid[8];
-        for (int d = 0; d < L; ++d) {
-            const uint64_t m = ballot(off < len && lv <= d);
-            fid[d] = base[d] + lanes_below(m);  // fiber number if this record starts one
-            base[d] += (uint32_t)__popcll(m);
-        }
-        if (off < len) {
-            // level d (1-based) fiber starts here when lv <= d-1; leaves always start
-            for (int d = 1; d <= a.r; ++d) {
-                const bool starts = (d == a.r) || (lv <= d - 1);
-                if (!starts) continue;
-                const uint32_t f = (d == a.r) ? e : fid[d - 1];
-                ((CT*)a.out_crd[d - 1])[f] = ((const CT*)a.crd[a.sigma[d - 1]])[e];
-                // a new parent at level d-1 (or the root for d = 1) records its first child
-                if (d == 1) {
-                    if (e == 0) ((PT*)a.pos[0])[0] = 0;
-                } else if (lv <= d - 2) {
-                    ((PT*)a.pos[d - 1])[fid[d - 2]] = (PT)f;
                 }
             }
         }
-    }
-    if (tid == 0 && start + len == a.n) {
-        // closing offsets: pos_d[F_{d-1}] = F_d
-        ((PT*)a.pos[0])[1] = (PT)(L >= 1 ? (s_excl[0] + s_wsum[0][0] + s_wsum[0][1] + s_wsum[0][2] + s_wsum[0][3]) : a.n);
-        for (int d = 2; d <= a.r; ++d) {
-            const uint32_t fprev = s_excl[d - 2] + s_wsum[d - 2][0] + s_wsum[d - 2][1] + s_wsum[d - 2][2] + s_wsum[d - 2][3];
-            const uint32_t fcur = (d == a.r) ? a.n
-                : s_excl[d - 1] + s_wsum[d - 1][0] + s_wsum[d - 1][1] + s_wsum[d - 1][2] + s_wsum[d - 1][3];
-            ((PT*)a.pos[d - 1])[fprev] = (PT)fcur;
+        if (tid == 0 && start + len == a.n) {
+            // closing offsets: pos_d[F_{d-1}] = F_d
+            ((PT*)a.pos[0])[1] = (PT)(L >= 1 ? (s_excl[0] + s_wsum[0][0] + s_wsum[0][1] + s_wsum[0][2] + s_wsum[0][3]) : a.n);
+            for (int d = 2; d <= a.r; ++d) {
+                const uint32_t fprev = s_excl[d - 2] + s_wsum[d - 2][0] + s_wsum[d - 2][1] + s_wsum[d - 2][2] + s_wsum[d - 2][3];
+                const uint32_t fcur = (d == a.r) ? a.n
+                    : s_excl[d - 1] + s_wsum[d - 1][0] + s_wsum[d - 1][1] + s_wsum[d - 1][2] + s_wsum[d - 1][3];
+                ((PT*)a.pos[d - 1])[fprev] = (PT)fcur;
+            }
         }
+        __syncthreads();  // s_wsum / s_excl / s_t are rewritten by the next tile
     }
 }
 

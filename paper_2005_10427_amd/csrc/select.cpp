@@ -1,5 +1,5 @@
 // C ABI of the schedule selector: features of a request, the perceptron's training steps and
-// the AUTO choice between the three schedules.
+// the AUTO choice between the candidate schedules.
 #include "../../include/qsd_select.h"
 
 #include <hip/hip_runtime.h>
@@ -30,11 +30,11 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
-// selector workspace: counts | features | outputs
+// selector workspace: sampled counts | result of k_select (candidate, predictions, features)
 constexpr size_t kWsCounts = 0;
-constexpr size_t kWsFeat = 256;
 constexpr size_t kWsOut = 512;
 constexpr size_t kWsBytes = 1024;
+static_assert(QSD_FEAT_COUNTS * 4 <= kWsOut && kWsOut + kSelectOutFloats * 4 <= kWsBytes, "selector workspace");
 
 uint64_t splitmix_next(uint64_t& state) {
     state += 0x9E3779B97F4A7C15ull;
@@ -50,114 +50,128 @@ uint32_t mode_mask(const std::vector<int>& modes) {
     return m;
 }
 
-// Pass and key-bit counts of the three schedules (minimal, Top-K, full LSD) and the mode
-// sets whose joint changes size their buckets.
+// The candidate schedules of the selector and, for each valid one, the plan terms of its
+// groups as the library runs them; the mode sets whose joint changes size their buckets.
 struct PlanTerms {
-    int s1_plain_calls = 0, s1_bucket_calls = 0, s1_plain_bits = 0, s1_bucket_bits = 0;
-    int s2_plain_bits = 0, s2_bucket_bits = 0, s3_bits = 0;
-    uint32_t prefix1 = 0, prefix2 = 0;
+    int valid[kNOut] = {};
+    int gp[kNOut] = {}, sb[kNOut] = {};
+    uint32_t set[kNSets] = {};
 };
 
-PlanTerms plan_terms(int r, const int* bits, const int* in_order, const int* out_order) {
+constexpr int kCandSched[kNOut] = {kSchedMinimal, kSchedMinimal, kSchedTopK + 1, kSchedTopK + 2, kSchedTopK + 3,
+                                   kSchedLsd};
+constexpr uint32_t kCandFlags[kNOut] = {0u, kKeepBuckets, 0u, 0u, 0u, 0u};
+
+PlanTerms plan_terms(const qsd_desc* d, const int* bits) {
     PlanTerms t;
-    for (const Call& c : quesadilla_calls(r, in_order, out_order)) {
-        if (c.prefix.empty()) {
-            ++t.s1_plain_calls;
-            t.s1_plain_bits += bits[c.mode];
-        } else {
-            if (!t.s1_bucket_calls) t.prefix1 = mode_mask(c.prefix);
-            ++t.s1_bucket_calls;
-            t.s1_bucket_bits += bits[c.mode];
+    const int r = d->order;
+    int segmented[2] = {0, 0};
+    for (int c = 0; c < kNOut; ++c) {
+        const int sched = kCandSched[c];
+        if (sched >= kSchedTopK && sched - kSchedTopK > r - 2) continue;  // K = r - 1 is MINIMAL
+        if (sched == kSchedLsd && r < 2) continue;
+        PlanData p;
+        p.r = r;
+        p.nnz = d->nnz;
+        p.flags = kCandFlags[c];
+        for (int m = 0; m < r; ++m) {
+            p.ext[m] = d->extents[m];
+            p.bits[m] = bits[m];
+            p.in_order[m] = d->in_order[m];
+            p.out_order[m] = d->out_order[m];
+        }
+        if (!build_plan(p, sched)) continue;
+        t.valid[c] = 1;
+        for (const Group& g : p.groups) {
+            int passes = 0;
+            for (const auto& sk : g.subs) passes += (int)sk.passes.size();
+            if (g.segmented) {
+                t.sb[c] += g.key_bits;
+                if (c < 2) ++segmented[c];
+            } else {
+                t.gp[c] += passes;
+            }
         }
     }
-    const int K = std::max(0, std::min(2, r - 2));
-    int target[kMaxR], n = 0;
-    for (int i = 0; i < K; ++i) target[n++] = out_order[i];
-    for (int i = 0; i < r; ++i) {
-        bool head = false;
-        for (int j = 0; j < K; ++j) head |= out_order[j] == in_order[i];
-        if (!head) target[n++] = in_order[i];
-    }
-    for (const Call& c : quesadilla_calls(r, in_order, target)) {
-        if (c.prefix.empty())
-            t.s2_plain_bits += bits[c.mode];
-        else
-            t.s2_bucket_bits += bits[c.mode];
-    }
-    if (K > 0) {
-        for (int i = K; i < r; ++i) t.s2_bucket_bits += bits[out_order[i]];
-        t.prefix2 = mode_mask(std::vector<int>(out_order, out_order + K));
-    }
-    for (int m = 0; m < r; ++m) t.s3_bits += bits[m];
+    // keeping the buckets is a candidate of its own only where the minimal plan flattens some
+    if (t.valid[1] && segmented[1] == segmented[0]) t.valid[1] = 0;
+    for (const Call& c : quesadilla_calls(r, d->in_order, d->out_order))
+        if (!c.prefix.empty()) {
+            t.set[0] = mode_mask(c.prefix);
+            break;
+        }
+    for (int K = 1; K <= 3; ++K)
+        if (K <= r - 2) t.set[K] = mode_mask(std::vector<int>(d->out_order, d->out_order + K));
     return t;
 }
 
-double linear_count(uint32_t zero) {
-    const double M = (double)kFeatMapBits;
-    return zero == 0 ? M * std::log(M) : -M * std::log((double)zero / M);
-}
+uint32_t sample_size(uint64_t n) { return (uint32_t)std::min<uint64_t>(n, kFeatSample); }
 
-void finish_features(const qsd_desc* d, const PlanTerms& t, const int* bits, const uint32_t* counts, uint32_t S,
-                     uint32_t pairs, float* out) {
-    const int r = d->order;
-    const double n = (double)d->nnz;
-    double f[kNFeat] = {};
-    f[0] = d->nnz > 0 ? std::log2(n) / 32.0 : 0.0;
-    f[1] = r / 8.0;
-    for (int i = 0; i < std::min(r, 5); ++i) {
-        const int m = d->out_order[i];
-        const uint32_t zero = counts[3 * m], top = counts[3 * m + 1], change = counts[3 * m + 2];
-        f[2 + 4 * i] = bits[m] / 32.0;
-        f[3 + 4 * i] = S ? std::log2(1.0 + linear_count(zero)) / 24.0 : 0.0;
-        f[4 + 4 * i] = pairs ? (double)change / pairs : 0.0;
-        f[5 + 4 * i] = S ? (double)top / S : 0.0;
-    }
-    f[22] = t.s1_plain_calls / 8.0;
-    f[23] = t.s1_bucket_calls / 8.0;
-    f[24] = t.s1_plain_bits / 64.0;
-    f[25] = t.s1_bucket_bits / 64.0;
-    f[26] = t.s2_plain_bits / 64.0;
-    f[27] = t.s2_bucket_bits / 64.0;
-    f[28] = t.s3_bits / 64.0;
-    f[29] = (pairs && t.prefix1) ? (double)counts[3 * r] / pairs : 0.0;
-    f[30] = (pairs && t.prefix2) ? (double)counts[3 * (r + 1)] / pairs : 0.0;
-    f[31] = std::log2(1.0 + f[29] * n) / 32.0;
-    for (int i = 0; i < kNFeat; ++i) out[i] = (float)f[i];
-}
-
-qsd_status counts_impl(const qsd_desc* d, const void* const* in_crd, void* ws, size_t ws_bytes, hipStream_t s,
-                       const PlanTerms& t, uint32_t* counts, uint32_t* S_out, uint32_t* pairs_out) {
-    std::memset(counts, 0, sizeof(uint32_t) * QSD_FEAT_COUNTS);
-    const uint64_t n = (uint64_t)d->nnz;
-    const uint32_t S = (uint32_t)std::min<uint64_t>(n, kFeatSample);
+uint32_t sample_pairs(uint64_t n) {
+    const uint32_t S = sample_size(n);
     uint32_t pairs = 0;
     for (uint32_t k = 0; k < S; ++k)
         if ((uint64_t)k * n / S + 1 < n) ++pairs;
-    *S_out = S;
-    *pairs_out = pairs;
-    if (n == 0) return QSD_OK;
-    if (!in_crd) return QSD_ERR_NULL;
-    for (int m = 0; m < d->order; ++m)
-        if (!in_crd[m]) return QSD_ERR_NULL;
+    return pairs;
+}
+
+// k_feat for a request: its counts land at the start of the workspace (no host copy).
+qsd_status launch_counts(const qsd_desc* d, const void* const* in_crd, void* ws, size_t ws_bytes, hipStream_t s,
+                         const PlanTerms& t) {
+    const uint64_t n = (uint64_t)d->nnz;
+    if (n > 0) {
+        if (!in_crd) return QSD_ERR_NULL;
+        for (int m = 0; m < d->order; ++m)
+            if (!in_crd[m]) return QSD_ERR_NULL;
+    }
     if (!ws || ws_bytes < kWsBytes) return QSD_ERR_WORKSPACE;
     FeatArgs a{};
-    for (int m = 0; m < d->order; ++m) a.crd[m] = in_crd[m];
+    for (int m = 0; m < d->order; ++m) a.crd[m] = n ? in_crd[m] : nullptr;
     a.r = d->order;
-    a.S = S;
+    a.S = sample_size(n);
     a.n = n;
-    a.mask[0] = t.prefix1;
-    a.mask[1] = t.prefix2;
-    uint32_t* dev = (uint32_t*)((char*)ws + kWsCounts);
-    a.out = dev;
-    if (launch_feat(a, d->crd_type == QSD_I64 ? 8 : 4, s) != hipSuccess) return QSD_ERR_HIP;
-    if (hipMemcpyAsync(counts, dev, sizeof(uint32_t) * 3 * (d->order + 2), hipMemcpyDeviceToHost, s) != hipSuccess)
-        return QSD_ERR_HIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return QSD_ERR_HIP;
-    return QSD_OK;
+    for (int q = 0; q < kNSets; ++q) a.mask[q] = t.set[q];
+    a.out = (uint32_t*)((char*)ws + kWsCounts);
+    return launch_feat(a, d->crd_type == QSD_I64 ? 8 : 4, s) == hipSuccess ? QSD_OK : QSD_ERR_HIP;
 }
 
 void desc_bits(const qsd_desc* d, int* bits) {
     for (int m = 0; m < d->order; ++m) bits[m] = bits_for_extent(d->extents[m]);
+}
+
+// Sampling, features and (with params) the forward pass and the choice, on the device; one
+// copy of the result back and one synchronisation.  out: kSelectOutFloats floats.
+qsd_status select_impl(const qsd_desc* d, const void* const* in_crd, void* ws, size_t ws_bytes, hipStream_t s,
+                       const float* params, float margin, float* out) {
+    int bits[kMaxR];
+    desc_bits(d, bits);
+    const PlanTerms t = plan_terms(d, bits);
+    qsd_status st = launch_counts(d, in_crd, ws, ws_bytes, s, t);
+    if (st != QSD_OK) return st;
+    SelectArgs a{};
+    a.counts = (const uint32_t*)((char*)ws + kWsCounts);
+    a.r = d->order;
+    a.n = (double)d->nnz;
+    a.S = sample_size((uint64_t)d->nnz);
+    a.pairs = sample_pairs((uint64_t)d->nnz);
+    for (int i = 0; i < 5 && i < d->order; ++i) a.slot_mode[i] = d->out_order[i];
+    for (int m = 0; m < d->order; ++m) a.bits[m] = bits[m];
+    a.crd_bytes = d->crd_type == QSD_I64 ? 8 : 4;
+    a.val_bytes = d->val_type == QSD_F64 ? 8 : 4;
+    for (int c = 0; c < kNOut; ++c) {
+        a.valid[c] = t.valid[c];
+        a.gp[c] = t.gp[c];
+        a.sb[c] = t.sb[c];
+    }
+    for (int q = 0; q < kNSets; ++q) a.set_nonempty[q] = t.set[q] != 0;
+    a.params = params;
+    a.margin = margin;
+    a.out = (float*)((char*)ws + kWsOut);
+    if (launch_select(a, s) != hipSuccess ||
+        hipMemcpyAsync(out, a.out, kSelectOutFloats * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return QSD_ERR_HIP;
+    return QSD_OK;
 }
 
 }  // namespace
@@ -170,15 +184,48 @@ qsd_status qsd_select_workspace(size_t* bytes) {
     return QSD_OK;
 }
 
-qsd_status qsd_feature_counts(const qsd_desc* desc, const void* const* in_crd, void* ws, size_t ws_bytes,
-                              hipStream_t stream, uint32_t* counts_host, uint32_t* sample, uint32_t* pairs) {
-    if (!counts_host || !sample || !pairs) return QSD_ERR_NULL;
+qsd_status qsd_candidate(int32_t candidate, qsd_sched_t* sched, uint32_t* flags) {
+    if (!sched || !flags) return QSD_ERR_NULL;
+    if (candidate < 0 || candidate >= kNOut) return QSD_ERR_UNSUPPORTED;
+    *sched = (qsd_sched_t)kCandSched[candidate];
+    *flags = kCandFlags[candidate];
+    return QSD_OK;
+}
+
+qsd_status qsd_candidate_terms(const qsd_desc* desc, int32_t* valid_host, int32_t* passes_host,
+                               int32_t* bucket_bits_host) {
+    if (!valid_host) return QSD_ERR_NULL;
     const qsd_status st = desc_status(desc);
     if (st != QSD_OK) return st;
     int bits[kMaxR];
     desc_bits(desc, bits);
-    const PlanTerms t = plan_terms(desc->order, bits, desc->in_order, desc->out_order);
-    return counts_impl(desc, in_crd, ws, ws_bytes, stream, t, counts_host, sample, pairs);
+    const PlanTerms t = plan_terms(desc, bits);
+    for (int c = 0; c < kNOut; ++c) {
+        valid_host[c] = t.valid[c];
+        if (passes_host) passes_host[c] = t.valid[c] ? t.gp[c] : 0;
+        if (bucket_bits_host) bucket_bits_host[c] = t.valid[c] ? t.sb[c] : 0;
+    }
+    return QSD_OK;
+}
+
+qsd_status qsd_feature_counts(const qsd_desc* desc, const void* const* in_crd, void* ws, size_t ws_bytes,
+                              hipStream_t stream, uint32_t* counts_host, uint32_t* sample, uint32_t* pairs) {
+    if (!counts_host || !sample || !pairs) return QSD_ERR_NULL;
+    qsd_status st = desc_status(desc);
+    if (st != QSD_OK) return st;
+    int bits[kMaxR];
+    desc_bits(desc, bits);
+    const PlanTerms t = plan_terms(desc, bits);
+    std::memset(counts_host, 0, sizeof(uint32_t) * QSD_FEAT_COUNTS);
+    *sample = sample_size((uint64_t)desc->nnz);
+    *pairs = sample_pairs((uint64_t)desc->nnz);
+    if (desc->nnz == 0) return QSD_OK;
+    if ((st = launch_counts(desc, in_crd, ws, ws_bytes, stream, t)) != QSD_OK) return st;
+    if (hipMemcpyAsync(counts_host, (char*)ws + kWsCounts, sizeof(uint32_t) * 3 * (desc->order + kNSets),
+                       hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return QSD_ERR_HIP;
+    return QSD_OK;
 }
 
 qsd_status qsd_features(const qsd_desc* desc, const void* const* in_crd, void* ws, size_t ws_bytes,
@@ -186,12 +233,9 @@ qsd_status qsd_features(const qsd_desc* desc, const void* const* in_crd, void* w
     if (!feat_host) return QSD_ERR_NULL;
     qsd_status st = desc_status(desc);
     if (st != QSD_OK) return st;
-    int bits[kMaxR];
-    desc_bits(desc, bits);
-    const PlanTerms t = plan_terms(desc->order, bits, desc->in_order, desc->out_order);
-    uint32_t counts[QSD_FEAT_COUNTS], S = 0, pairs = 0;
-    if ((st = counts_impl(desc, in_crd, ws, ws_bytes, stream, t, counts, &S, &pairs)) != QSD_OK) return st;
-    finish_features(desc, t, bits, counts, S, pairs, feat_host);
+    float out[kSelectOutFloats];
+    if ((st = select_impl(desc, in_crd, ws, ws_bytes, stream, nullptr, 0.f, out)) != QSD_OK) return st;
+    std::copy(out + 8, out + 8 + kNFeat, feat_host);
     return QSD_OK;
 }
 
@@ -381,7 +425,7 @@ qsd_status qsd_model_load(const char* path, qsd_model_t* out) {
     float margin = 0.f;
     int64_t min_nnz = 0;
     std::vector<float> p(kNParam);
-    const bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "QSDMLP1", 8) == 0 &&
+    const bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "QSDMLP2", 8) == 0 &&
                     std::fread(&np, 4, 1, f) == 1 && np == kNParam && std::fread(&margin, 4, 1, f) == 1 &&
                     std::fread(&min_nnz, 8, 1, f) == 1 && std::fread(p.data(), 4, kNParam, f) == (size_t)kNParam;
     std::fclose(f);
@@ -396,41 +440,33 @@ void qsd_model_destroy(qsd_model_t m) {
 }
 
 qsd_status qsd_select(qsd_model_t model, const qsd_desc* desc, const void* const* in_crd, void* ws, size_t ws_bytes,
-                      hipStream_t stream, qsd_sched_t* chosen, float* predicted_host) {
-    if (!model || !chosen) return QSD_ERR_NULL;
+                      hipStream_t stream, int32_t* candidate, float* predicted_host) {
+    if (!model || !candidate) return QSD_ERR_NULL;
     qsd_status st = desc_status(desc);
     if (st != QSD_OK) return st;
-    *chosen = QSD_SCHED_MINIMAL;
+    *candidate = 0;
     if (desc->nnz < model->min_nnz) return QSD_OK;  // too small for the choice to pay for itself
-    float feat[kNFeat];
-    if ((st = qsd_features(desc, in_crd, ws, ws_bytes, stream, feat)) != QSD_OK) return st;
-    for (float v : feat)
-        if (!std::isfinite(v) || v < 0.f || v > 4.f) return QSD_OK;  // outside the trained range
-    if (!ws || ws_bytes < kWsBytes) return QSD_ERR_WORKSPACE;
-    float* fdev = (float*)((char*)ws + kWsFeat);
-    float* ydev = (float*)((char*)ws + kWsOut);
-    float y[kNOut];
-    if (hipMemcpyAsync(fdev, feat, sizeof(feat), hipMemcpyHostToDevice, stream) != hipSuccess ||
-        launch_mlp_fwd(model->params, fdev, 1, nullptr, nullptr, ydev, stream) != hipSuccess ||
-        hipMemcpyAsync(y, ydev, sizeof(y), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess)
-        return QSD_ERR_HIP;
-    if (predicted_host) std::copy(y, y + kNOut, predicted_host);
-    int best = 0;
-    for (int s = 1; s < kNOut; ++s)
-        if (y[s] < y[0] - model->margin && y[s] < y[best]) best = s;
-    *chosen = (qsd_sched_t)(QSD_SCHED_MINIMAL + best);
+    float out[kSelectOutFloats];
+    if ((st = select_impl(desc, in_crd, ws, ws_bytes, stream, model->params, model->margin, out)) != QSD_OK)
+        return st;
+    int32_t c = 0;
+    std::memcpy(&c, &out[0], 4);
+    if (c < 0 || c >= kNOut) return QSD_ERR_DEVICE;
+    if (predicted_host) std::copy(out + 1, out + 1 + kNOut, predicted_host);
+    *candidate = c;
     return QSD_OK;
 }
 
 qsd_status qsd_plan_auto(qsd_model_t model, const qsd_desc* desc, const void* const* in_crd, void* ws,
-                         size_t ws_bytes, hipStream_t stream, qsd_plan_t* out, qsd_sched_t* chosen) {
+                         size_t ws_bytes, hipStream_t stream, qsd_plan_t* out, int32_t* candidate) {
     if (!out) return QSD_ERR_NULL;
-    qsd_sched_t s = QSD_SCHED_MINIMAL;
-    const qsd_status st = qsd_select(model, desc, in_crd, ws, ws_bytes, stream, &s, nullptr);
+    int32_t c = 0;
+    const qsd_status st = qsd_select(model, desc, in_crd, ws, ws_bytes, stream, &c, nullptr);
     if (st != QSD_OK) return st;
-    if (chosen) *chosen = s;
-    return qsd_plan(desc, s, out);
+    if (candidate) *candidate = c;
+    qsd_desc d = *desc;
+    d.flags |= kCandFlags[c];
+    return qsd_plan(&d, (qsd_sched_t)kCandSched[c], out);
 }
 
 }  // extern "C"

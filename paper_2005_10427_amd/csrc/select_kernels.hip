@@ -1,4 +1,4 @@
-// Schedule-selector kernels.  The network is tiny (6467 parameters), so every kernel keeps
+// Schedule-selector kernels.  The network is tiny (7174 parameters), so every kernel keeps
 // the weights it needs in LDS and gives one thread a whole row (forward, deltas) or a whole
 // parameter (gradient sums over the rows, in row order, so results are reproducible).
 #include "select_kernels.h"
@@ -50,13 +50,25 @@ __global__ void __launch_bounds__(kThreads) k_feat(FeatArgs a) {
         for (int i = tid; i < (int)kFeatBuckets; i += kThreads) s_bkt[i] = 0;
         __syncthreads();
         const CT* c = (const CT*)a.crd[b];
-        for (uint32_t k = tid; k < a.S; k += kThreads) {
-            const uint64_t j = (uint64_t)k * a.n / a.S;
-            const CT x = c[j];
-            const uint64_t h = mix64((uint64_t)(int64_t)x);
-            atomicOr(&s_map[(uint32_t)(h & 0xFFFF) >> 5], 1u << (uint32_t)(h & 31));
-            atomicAdd(&s_bkt[(uint32_t)(h >> 16) & (kFeatBuckets - 1)], 1u);
-            if (j + 1 < a.n && c[j + 1] != x) ++change;
+        // U samples per thread per round, all loads issued before any is used
+        constexpr int U = 16;
+        for (uint32_t k0 = tid; k0 < a.S; k0 += kThreads * U) {
+            CT x[U], y[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t k = k0 + u * kThreads;
+                const uint64_t j = (uint64_t)k * a.n / a.S;
+                x[u] = k < a.S ? c[j] : CT(0);
+                y[u] = (k < a.S && j + 1 < a.n) ? c[j + 1] : x[u];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (k0 + u * kThreads >= a.S) continue;
+                const uint64_t h = mix64((uint64_t)(int64_t)x[u]);
+                atomicOr(&s_map[(uint32_t)(h & 0xFFFF) >> 5], 1u << (uint32_t)(h & 31));
+                atomicAdd(&s_bkt[(uint32_t)(h >> 16) & (kFeatBuckets - 1)], 1u);
+                if (y[u] != x[u]) ++change;
+            }
         }
         barrier_after_lds_atomics();
         uint32_t zero = 0, top = 0;
@@ -72,16 +84,28 @@ __global__ void __launch_bounds__(kThreads) k_feat(FeatArgs a) {
         }
     } else {
         const uint32_t mask = a.mask[b - a.r];
-        for (uint32_t k = tid; k < a.S; k += kThreads) {
-            const uint64_t j = (uint64_t)k * a.n / a.S;
-            if (j + 1 >= a.n) continue;
-            bool d = false;
-            for (int m = 0; m < a.r; ++m)
-                if ((mask >> m) & 1u) {
-                    const CT* c = (const CT*)a.crd[m];
-                    d |= c[j] != c[j + 1];
+        constexpr int U = 8;
+        for (uint32_t k0 = tid; mask && k0 < a.S; k0 += kThreads * U) {
+            bool d[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) d[u] = false;
+            for (int m = 0; m < a.r; ++m) {
+                if (!((mask >> m) & 1u)) continue;
+                const CT* c = (const CT*)a.crd[m];
+                CT x[U], y[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t k = k0 + u * kThreads;
+                    const uint64_t j = (uint64_t)k * a.n / a.S;
+                    const bool ok = k < a.S && j + 1 < a.n;
+                    x[u] = ok ? c[j] : CT(0);
+                    y[u] = ok ? c[j + 1] : CT(0);
                 }
-            change += d ? 1u : 0u;
+#pragma unroll
+                for (int u = 0; u < U; ++u) d[u] |= x[u] != y[u];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) change += d[u] ? 1u : 0u;
         }
         change = block_reduce<uint32_t>(change, s_tmp, false);
         if (tid == 0) {
@@ -131,6 +155,78 @@ __global__ void __launch_bounds__(kThreads) k_mlp_fwd(const float* __restrict__ 
         for (int i = 0; i < kH2; ++i) H2[(size_t)row * kH2 + i] = h2[i];
 }
 
+// The features of one request from its sampled counts (in double precision, as defined in the
+// selector's header), then the forward pass (the same sums, in the same order, as k_mlp_fwd)
+// and the choice: candidate 0 unless a valid candidate is predicted faster by more than the
+// margin.  One wave.
+__global__ void __launch_bounds__(64) k_select(SelectArgs a) {
+    __shared__ float x[kNFeat];
+    __shared__ float h1[kH1];
+    __shared__ float h2[kH2];
+    __shared__ float y[kNOut];
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        double f[kNFeat];
+        for (int i = 0; i < kNFeat; ++i) f[i] = 0.0;
+        const double M = (double)kFeatMapBits;
+        f[0] = a.n > 0 ? log2(a.n) / 32.0 : 0.0;
+        f[1] = a.r / 8.0;
+        for (int s = 0; s < 5 && s < a.r; ++s) {
+            const int m = a.slot_mode[s];
+            const uint32_t zero = a.counts[3 * m], top = a.counts[3 * m + 1], change = a.counts[3 * m + 2];
+            const double D = zero == 0 ? M * log(M) : -M * log((double)zero / M);
+            f[2 + 4 * s] = a.bits[m] / 32.0;
+            f[3 + 4 * s] = a.S ? log2(1.0 + D) / 24.0 : 0.0;
+            f[4 + 4 * s] = a.pairs ? (double)change / a.pairs : 0.0;
+            f[5 + 4 * s] = a.S ? (double)top / a.S : 0.0;
+        }
+        f[22] = a.crd_bytes / 8.0;
+        f[23] = a.val_bytes / 8.0;
+        for (int c = 0; c < kNOut; ++c) {
+            if (!a.valid[c]) continue;
+            f[24 + 2 * c] = a.gp[c] / 16.0;
+            f[25 + 2 * c] = a.sb[c] / 64.0;
+        }
+        for (int q = 0; q < kNSets; ++q)
+            if (a.pairs && a.set_nonempty[q]) f[36 + q] = (double)a.counts[3 * (a.r + q)] / a.pairs;
+        for (int i = 0; i < kNFeat; ++i) {
+            x[i] = (float)f[i];
+            a.out[8 + i] = x[i];
+        }
+    }
+    __syncthreads();
+    if (!a.params) return;
+    const float* w = a.params;
+    {
+        float s = w[kOffB1 + tid];
+        for (int i = 0; i < kNFeat; ++i) s += w[kOffW1 + tid * kNFeat + i] * x[i];
+        h1[tid] = s > 0.f ? s : 0.f;
+    }
+    __syncthreads();
+    {
+        float s = w[kOffB2 + tid];
+        for (int i = 0; i < kH1; ++i) s += w[kOffW2 + tid * kH1 + i] * h1[i];
+        h2[tid] = s > 0.f ? s : 0.f;
+    }
+    __syncthreads();
+    if (tid < kNOut) {
+        float s = w[kOffB3 + tid];
+        for (int i = 0; i < kH2; ++i) s += w[kOffW3 + tid * kH2 + i] * h2[i];
+        y[tid] = s;
+        a.out[1 + tid] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        bool in_range = true;
+        for (int i = 0; i < kNFeat; ++i) in_range &= (x[i] == x[i]) && x[i] >= 0.f && x[i] <= 4.f;
+        int best = 0;
+        if (in_range)
+            for (int c = 1; c < kNOut; ++c)
+                if (a.valid[c] && y[c] < y[0] - a.margin && y[c] < y[best]) best = c;
+        a.out[0] = __int_as_float(best);
+    }
+}
+
 __global__ void __launch_bounds__(kThreads) k_mlp_delta(const float* __restrict__ P, const float* __restrict__ H1,
                                                         const float* __restrict__ H2, const float* __restrict__ Y,
                                                         const float* __restrict__ T, int n, float* D1, float* D2,
@@ -146,7 +242,8 @@ __global__ void __launch_bounds__(kThreads) k_mlp_delta(const float* __restrict_
     float d3[kNOut], err = 0.f;
 #pragma unroll
     for (int k = 0; k < kNOut; ++k) {
-        const float e = Y[(size_t)row * kNOut + k] - T[(size_t)row * kNOut + k];
+        const float t = T[(size_t)row * kNOut + k];
+        const float e = t == t ? Y[(size_t)row * kNOut + k] - t : 0.f;  // a NaN target: no error
         err += e * e;
         d3[k] = e * scale;
         D3[(size_t)row * kNOut + k] = d3[k];
@@ -241,8 +338,13 @@ unsigned blocks(long long work) { return (unsigned)((work + kThreads - 1) / kThr
 
 }  // namespace
 
+hipError_t launch_select(const SelectArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_feat(const FeatArgs& a, int crd_bytes, hipStream_t s) {
-    const dim3 grid(a.r + 2);
+    const dim3 grid(a.r + kNSets);
     if (crd_bytes == 8)
         hipLaunchKernelGGL(k_feat<int64_t>, grid, dim3(kThreads), 0, s, a);
     else

@@ -80,6 +80,9 @@ def load():
                                   _VP, ctypes.c_size_t, _VP]
     lib.qsd_transpose_noalloc.argtypes = [_VP, ctypes.c_int64, ctypes.POINTER(_VP), _VP, ctypes.POINTER(_VP), _VP,
                                           _VP]
+    lib.qsd_csf_transpose_workspace.argtypes = [_VP, ctypes.POINTER(ctypes.c_size_t)]
+    lib.qsd_csf_transpose.argtypes = [_VP, ctypes.c_int64, ctypes.POINTER(_VP), ctypes.POINTER(_VP), _VP,
+                                      ctypes.POINTER(_VP), ctypes.POINTER(_VP), _VP, _VP, _VP, ctypes.c_size_t, _VP]
     lib.qsd_csf_workspace.argtypes = [_VP, ctypes.POINTER(ctypes.c_size_t)]
     lib.qsd_pack_csf.argtypes = [_VP, ctypes.c_int64, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                                  ctypes.POINTER(_VP), _VP, _VP, ctypes.c_size_t, _VP]
@@ -125,15 +128,20 @@ def load():
     lib.qsd_model_destroy.argtypes = [_VP]
     lib.qsd_model_destroy.restype = None
     lib.qsd_select.argtypes = [_VP, ctypes.POINTER(qsd_desc), ctypes.POINTER(_VP), _VP, ctypes.c_size_t, _VP,
-                               ctypes.POINTER(ctypes.c_int), F]
+                               ctypes.POINTER(ctypes.c_int32), F]
     lib.qsd_plan_auto.argtypes = [_VP, ctypes.POINTER(qsd_desc), ctypes.POINTER(_VP), _VP, ctypes.c_size_t, _VP,
-                                  ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int)]
+                                  ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int32)]
+    lib.qsd_candidate.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint32)]
+    I32 = ctypes.POINTER(ctypes.c_int32)
+    lib.qsd_candidate_terms.argtypes = [ctypes.POINTER(qsd_desc), I32, I32, I32]
     for name in ("qsd_select_workspace", "qsd_feature_counts", "qsd_features", "qsd_mlp_init", "qsd_mlp_forward",
                  "qsd_mlp_backward_workspace", "qsd_mlp_backward", "qsd_mlp_adam", "qsd_mlp_train_workspace",
-                 "qsd_mlp_train", "qsd_model_create", "qsd_model_load", "qsd_select", "qsd_plan_auto"):
+                 "qsd_mlp_train", "qsd_model_create", "qsd_model_load", "qsd_select", "qsd_plan_auto",
+                 "qsd_candidate", "qsd_candidate_terms"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("qsd_plan", "qsd_plan_workspace", "qsd_plan_describe", "qsd_transpose", "qsd_transpose_noalloc",
                  "qsd_csf_workspace", "qsd_pack_csf", "qsd_device_status", "qsd_profile_start",
+                 "qsd_csf_transpose_workspace", "qsd_csf_transpose",
                  "qsd_profile_stop", "qsd_batch_plan", "qsd_batch_set_tuning", "qsd_batch_get_tuning",
                  "qsd_batch_workspace", "qsd_batch_workspace_max", "qsd_batch_bind", "qsd_batch_transpose",
                  "qsd_batch_tune", "qsd_batch_graph", "qsd_graph_launch"):
@@ -211,6 +219,19 @@ def qsd_csf_workspace(plan):
 def qsd_pack_csf(plan, nnz, sorted_crd, pos, crd, fiber_counts, ws, ws_bytes, stream):
     _check(load().qsd_pack_csf(plan, int(nnz), _ptrs(sorted_crd), _ptrs(pos), _ptrs(crd), fiber_counts,
                                ws, int(ws_bytes), stream), "qsd_pack_csf")
+
+
+def qsd_csf_transpose_workspace(plan):
+    n = ctypes.c_size_t()
+    _check(load().qsd_csf_transpose_workspace(plan, ctypes.byref(n)), "qsd_csf_transpose_workspace")
+    return n.value
+
+
+def qsd_csf_transpose(plan, nnz, in_pos, in_crd, in_val, out_pos, out_crd, out_val, fiber_counts, ws, ws_bytes,
+                      stream):
+    _check(load().qsd_csf_transpose(plan, int(nnz), _ptrs(in_pos), _ptrs(in_crd), in_val, _ptrs(out_pos),
+                                    _ptrs(out_crd), out_val, fiber_counts, ws, int(ws_bytes), stream),
+           "qsd_csf_transpose")
 
 
 def qsd_device_status(ws, stream):
@@ -316,8 +337,31 @@ def qsd_graph_destroy(graph):
     load().qsd_graph_destroy(graph)
 
 
-NFEAT, NSCHED, MLP_NPARAM, FEAT_COUNTS = 32, 3, 6467, 3 * (MAX_ORDER + 2)
-SCHED_NAMES = {1: "minimal", 2: "top2", 3: "lsd"}
+NFEAT, NCAND, MLP_NPARAM, FEAT_COUNTS = 40, 6, 7174, 3 * (MAX_ORDER + 4)
+# the selector's candidates: (name, schedule for qsd_plan, extra plan flags)
+CANDIDATES = (("minimal", "minimal", 0), ("minimal-buckets", "minimal", QSD_KEEP_BUCKETS), ("topk1", "topk1", 0),
+              ("topk2", "topk2", 0), ("topk3", "topk3", 0), ("lsd", "lsd", 0))
+CAND_NAMES = tuple(c[0] for c in CANDIDATES)
+
+
+def qsd_candidate(c):
+    """(schedule code, extra plan flags) of candidate c."""
+    sc = ctypes.c_int()
+    fl = ctypes.c_uint32()
+    _check(load().qsd_candidate(int(c), ctypes.byref(sc), ctypes.byref(fl)), "qsd_candidate")
+    return sc.value, fl.value
+
+
+def qsd_candidate_terms(desc):
+    """[(valid, global digit passes, bucketed key bits)] of every candidate of a request."""
+    d, _keep = _desc(*desc)
+    v, gp, sb = (ctypes.c_int32 * NCAND)(), (ctypes.c_int32 * NCAND)(), (ctypes.c_int32 * NCAND)()
+    _check(load().qsd_candidate_terms(ctypes.byref(d), v, gp, sb), "qsd_candidate_terms")
+    return [(bool(v[c]), gp[c], sb[c]) for c in range(NCAND)]
+
+
+def qsd_candidates_valid(desc):
+    return [t[0] for t in qsd_candidate_terms(desc)]
 
 
 def qsd_select_workspace():
@@ -401,20 +445,20 @@ def qsd_model_destroy(model):
 
 
 def qsd_select(model, desc, in_crd, ws, ws_bytes, stream):
-    """Returns (chosen schedule code, predicted log2 ms of the three schedules)."""
+    """Returns (chosen candidate, predicted log2 ms of every candidate)."""
     d, _keep = _desc(*desc)
-    ch = ctypes.c_int()
-    pred = (ctypes.c_float * NSCHED)()
+    ch = ctypes.c_int32()
+    pred = (ctypes.c_float * NCAND)()
     _check(load().qsd_select(model, ctypes.byref(d), _ptrs(in_crd), ws, int(ws_bytes), stream, ctypes.byref(ch),
                              pred), "qsd_select")
     return ch.value, list(pred)
 
 
 def qsd_plan_auto(model, desc, in_crd, ws, ws_bytes, stream):
-    """Returns (plan handle, chosen schedule code)."""
+    """Returns (plan handle, chosen candidate)."""
     d, _keep = _desc(*desc)
     h = _VP()
-    ch = ctypes.c_int()
+    ch = ctypes.c_int32()
     _check(load().qsd_plan_auto(model, ctypes.byref(d), _ptrs(in_crd), ws, int(ws_bytes), stream,
                                 ctypes.byref(h), ctypes.byref(ch)), "qsd_plan_auto")
     return h.value, ch.value
@@ -424,7 +468,7 @@ def write_model_file(path, params, margin, min_nnz=0):
     """The selector weights file read by qsd_model_load."""
     import struct
     with open(path, "wb") as f:
-        f.write(b"QSDMLP1\0")
+        f.write(b"QSDMLP2\0")
         f.write(struct.pack("<ifq", MLP_NPARAM, float(margin), int(min_nnz)))
         f.write(struct.pack(f"<{MLP_NPARAM}f", *[float(x) for x in params]))
 
@@ -511,6 +555,28 @@ class Plan:
         if ws is None:
             return 0  # nothing has run
         return qsd_device_status(ws.data_ptr(), s.cuda_stream)
+
+    def transpose_csf(self, in_pos, in_crd, in_val, stream=None):
+        """CSF (levels in in_order) -> CSF (levels in out_order): returns (pos list, crd list,
+        values, fiber counts as a host list)."""
+        torch = self.torch
+        n = int(in_val.shape[0])
+        dev = in_val.device
+        pt = torch.int64 if self.crd_dtype == torch.int64 else torch.int32
+        pos = [torch.empty(2 if d == 0 else max(n, 1) + 1, dtype=pt, device=dev) for d in range(self.r)]
+        crd = [torch.empty(max(n, 1), dtype=self.crd_dtype, device=dev) for _ in range(self.r)]
+        val = torch.empty_like(in_val)
+        fc = torch.empty(self.r + 1, dtype=torch.int64, device=dev)
+        wsb = qsd_csf_transpose_workspace(self.handle)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        qsd_csf_transpose(self.handle, n, [p.data_ptr() for p in in_pos], [c.data_ptr() for c in in_crd],
+                          in_val.data_ptr(), [p.data_ptr() for p in pos], [c.data_ptr() for c in crd],
+                          val.data_ptr(), fc.data_ptr(), ws.data_ptr(), wsb, s.cuda_stream)
+        self._last_ws = ws
+        counts = fc.cpu().tolist()
+        return ([pos[d][:counts[d] + 1] for d in range(self.r)], [crd[d][:counts[d + 1]] for d in range(self.r)],
+                val, counts)
 
     def pack_csf(self, sorted_crd, nnz=None, stream=None):
         """CSF of a tensor sorted under out_order: returns (pos list, crd list, fiber counts)."""

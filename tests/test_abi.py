@@ -221,13 +221,23 @@ def test_selector_host_parts(lib):
     # initial weights: same SplitMix64 stream and rounding as the oracle's
     for seed in (0, 7, 2 ** 63 + 5):
         assert np.array_equal(np.array(qsd.qsd_mlp_init(seed), dtype=np.float64), OM.init_params(seed))
-    # an empty request needs no device work: the features come from the plan terms alone
-    for tau, sigma in [((0, 1, 2), (0, 2, 1)), ((2, 0, 1, 3), (1, 3, 0, 2))]:
-        ext = (100, 9, 1000, 5)[:len(tau)]
-        f = qsd.qsd_features((len(tau), 0, ext, qsd.QSD_I32, qsd.QSD_F64, tau, sigma), [0] * len(tau), None, 0,
-                             None)
-        want = OF.features([np.zeros(0, np.int32)] * len(tau), ext, tau, sigma)
-        assert np.allclose(f, want, atol=1e-7)
+    # the candidates' plan terms (host planner) equal the oracle's restatement of the library's
+    # grouping, flattening and digit rules, for every order pair up to 5 modes and extents that
+    # make flattening go either way
+    import itertools
+    for r, ext in [(2, (300, 9)), (3, (4, 16, 256)), (3, (500000, 20000, 2000000)), (4, (1 << 20, 1 << 17, 1 << 10, 64)),
+                   (4, (9, 1, 40, 3000)), (5, (40, 300, 50, 2000, 30)), (5, (2000000, 300000, 50000, 2000, 100))]:
+        perms = list(itertools.permutations(range(r)))
+        for tau in perms[:: max(1, len(perms) // 6)]:
+            for sigma in perms:
+                got = qsd.qsd_candidate_terms((r, 1000, ext, qsd.QSD_I32, qsd.QSD_F64, tau, sigma))
+                want, _ = OF.plan_terms(ext, tau, sigma)
+                assert [g[0] for g in got] == [w is not None for w in want], (ext, tau, sigma)
+                assert [g[1:] for g in got if g[0]] == [w for w in want if w is not None], (ext, tau, sigma)
+    for c in range(qsd.NCAND):
+        sc, fl = qsd.qsd_candidate(c)
+        name, sched, flags = qsd.CANDIDATES[c]
+        assert sc == qsd.sched_code(sched) and fl == flags
     with pytest.raises(qsd.QsdError) as e:  # workspace too small for a real request
         qsd.qsd_features((3, 10, (4, 4, 4), qsd.QSD_I32, qsd.QSD_F64, (0, 1, 2), (2, 1, 0)), [0x1000] * 3, 0x1000,
                          16, None)

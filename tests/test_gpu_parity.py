@@ -253,3 +253,65 @@ def test_csf_pack_matches_oracle(gpu_lib):
         for d in range(r):
             assert pos[d].cpu().tolist() == want_pos[d], f"pos level {d + 1}"
             assert lev[d].cpu().tolist() == want_lev[d], f"crd level {d + 1}"
+
+
+@pytest.mark.parametrize("crd_dtype", ["int32", "int64"])
+def test_csf_to_csf_matches_oracle(gpu_lib, crd_dtype):
+    """CSF (levels in tau) -> CSF (levels in sigma) against the oracle's unpack -> transpose ->
+    pack, on tensors with duplicate coordinates (separate leaves), r = 1..5, ragged sizes."""
+    import torch
+    from oracle import csf
+    rng = np.random.default_rng(31 if crd_dtype == "int32" else 32)
+    cases = [(3, 1, (1, 1, 1)), (2, 1, (5, 7))]
+    for _ in range(10):
+        r = int(rng.integers(1, 6))
+        cases.append((r, int(rng.integers(1, 30000)), tuple(int(x) for x in rng.integers(1, 40, size=r))))
+    for r, n, ext in cases:
+        tau = tuple(int(x) for x in rng.permutation(r))
+        sigma = tuple(int(x) for x in rng.permutation(r))
+        T = make_tensor(ext, n, zipf=[1.0] * r, in_order=tau, seed=n + r, distinct=False,
+                        crd_dtype=np.dtype(crd_dtype))
+        note(f"csf->csf r={r} n={n} ext={ext} tau={tau} sigma={sigma} {crd_dtype}")
+        in_pos, in_lev = csf.pack_csf([c.tolist() for c in T.crd], tau)
+        td = torch.int64 if crd_dtype == "int64" else torch.int32
+        ip = [torch.tensor(p, dtype=td, device="cuda") for p in in_pos]
+        ic = [torch.tensor(lv if lv else [0], dtype=td, device="cuda") for lv in in_lev]
+        iv = torch.from_numpy(T.val).cuda()
+        P = gpu_lib.Plan(ext, tau, sigma, n, crd_dtype, "float64")
+        pos, lev, val, counts = P.transpose_csf(ip, ic, iv)
+        torch.cuda.synchronize()
+        assert P.device_status() == 0
+        # the oracle: expand the input tree, transpose, pack under sigma
+        coo = csf.unpack_csf(in_pos, in_lev, tau)
+        for m in range(r):
+            assert coo[m] == T.crd[m].tolist()  # (the oracle round trip itself)
+        w_crd, w_val = oracle_transpose([np.asarray(c, dtype=T.crd[0].dtype) for c in coo], T.val, sigma)
+        want_pos, want_lev = csf.pack_csf([c.tolist() for c in w_crd], sigma)
+        assert counts == [1] + [len(lv) for lv in want_lev]
+        for d in range(r):
+            assert pos[d].cpu().tolist() == want_pos[d], f"pos level {d + 1}"
+            assert lev[d].cpu().tolist() == want_lev[d], f"crd level {d + 1}"
+        assert np.array_equal(val.cpu().numpy().view(np.uint64), w_val.view(np.uint64)), "values"
+
+
+def test_csf_to_csf_plain_workload(gpu_lib):
+    """The 3-mode workload shrunk to 1.5e5 nonzeros, its CSF in the input order transposed to the
+    CSF of every other order."""
+    import torch
+    from oracle import csf
+    T = config_tensor("plain", nnz=150_000)
+    in_pos, in_lev = csf.pack_csf([c.tolist() for c in T.crd], T.in_order)
+    ip = [torch.tensor(p, dtype=torch.int32, device="cuda") for p in in_pos]
+    ic = [torch.tensor(lv, dtype=torch.int32, device="cuda") for lv in in_lev]
+    iv = torch.from_numpy(T.val).cuda()
+    for sigma in CONFIGS["plain"]["sigmas"]:
+        note(f"csf->csf plain sigma={sigma}")
+        P = gpu_lib.Plan(T.extents, T.in_order, sigma, T.nnz)
+        pos, lev, val, counts = P.transpose_csf(ip, ic, iv)
+        torch.cuda.synchronize()
+        assert P.device_status() == 0
+        w_crd, w_val = oracle_transpose(T.crd, T.val, sigma)
+        want_pos, want_lev = csf.pack_csf([c.tolist() for c in w_crd], sigma)
+        for d in range(3):
+            assert pos[d].cpu().tolist() == want_pos[d] and lev[d].cpu().tolist() == want_lev[d], (sigma, d)
+        assert np.array_equal(val.cpu().numpy().view(np.uint64), w_val.view(np.uint64))

@@ -54,16 +54,18 @@ def test_feature_counts_and_features_match_oracle(gpu_lib, case):
     s = torch.cuda.current_stream().cuda_stream
     counts, S, pairs = qsd.qsd_feature_counts(_desc(qsd, T, sigma), [c.data_ptr() for c in crd], ws.data_ptr(),
                                               wsb, s)
-    pt = OF.plan_terms(ext, tau, sigma)
-    per_mode, mch, S0, P0 = OF.counts(T.crd, masks=[pt["prefix1"], pt["prefix2"]])
+    terms, Q = OF.plan_terms(ext, tau, sigma)
+    per_mode, mch, S0, P0 = OF.counts(T.crd, masks=Q)
     assert (S, pairs) == (S0, P0)
     r = len(ext)
-    for m in range(r):
-        assert tuple(counts[3 * m:3 * m + 3]) == per_mode[m], m
-    assert counts[3 * r] == (mch[0] if pt["prefix1"] else 0)
-    assert counts[3 * (r + 1)] == (mch[1] if pt["prefix2"] else 0)
+    if nnz:
+        for m in range(r):
+            assert tuple(counts[3 * m:3 * m + 3]) == per_mode[m], m
+        for q in range(4):
+            assert counts[3 * (r + q)] == (mch[q] if Q[q] else 0), q
+    assert qsd.qsd_candidates_valid(_desc(qsd, T, sigma)) == [t is not None for t in terms]
     f = np.array(qsd.qsd_features(_desc(qsd, T, sigma), [c.data_ptr() for c in crd], ws.data_ptr(), wsb, s))
-    want = OF.features(T.crd, ext, tau, sigma)
+    want = OF.features(T.crd, ext, tau, sigma, T.crd[0].dtype.itemsize, 8)
     assert np.allclose(f, want, rtol=1e-6, atol=1e-6)
 
 
@@ -81,13 +83,14 @@ def test_forward_and_backward_match_oracle(gpu_lib, n):
     import torch
     qsd = gpu_lib
     rng = np.random.default_rng(n)
-    X = rng.uniform(0, 1, size=(n, 32)).astype(np.float32).astype(np.float64)
-    T = rng.normal(0, 2, size=(n, 3)).astype(np.float32).astype(np.float64)
+    X = rng.uniform(0, 1, size=(n, OM.SIZES[0])).astype(np.float32).astype(np.float64)
+    T = rng.normal(0, 2, size=(n, OM.SIZES[3])).astype(np.float32).astype(np.float64)
+    T[rng.uniform(size=T.shape) < 0.3] = np.nan  # candidates that do not exist for a row
     theta = _theta(n)
     P, Xd, Td = _t(theta), _t(X), _t(T)
     H1 = torch.empty(n, 64, device="cuda")
     H2 = torch.empty(n, 64, device="cuda")
-    Y = torch.empty(n, 3, device="cuda")
+    Y = torch.empty(n, OM.SIZES[3], device="cuda")
     s = torch.cuda.current_stream().cuda_stream
     qsd.qsd_mlp_forward(P.data_ptr(), Xd.data_ptr(), n, H1.data_ptr(), H2.data_ptr(), Y.data_ptr(), s)
     h1, h2, y = OM.forward(theta, X)
@@ -130,8 +133,10 @@ def test_minibatch_training_matches_oracle(gpu_lib):
     qsd = gpu_lib
     rng = np.random.default_rng(4)
     n, epochs, batch, lr = 100, 3, 32, 1e-3
-    X = rng.uniform(0, 1, size=(n, 32)).astype(np.float32).astype(np.float64)
-    T = np.stack([X[:, 0] + X[:, 1], 2 * X[:, 2], -X[:, 3]], axis=1).astype(np.float32).astype(np.float64)
+    X = rng.uniform(0, 1, size=(n, OM.SIZES[0])).astype(np.float32).astype(np.float64)
+    T = np.stack([X[:, 0] + X[:, 1], 2 * X[:, 2], -X[:, 3], X[:, 4] * X[:, 5], X[:, 6], X[:, 7] - X[:, 8]],
+                 axis=1).astype(np.float32).astype(np.float64)
+    T[:, 4][X[:, 9] < 0.5] = np.nan
     theta0 = np.array(qsd.qsd_mlp_init(21), dtype=np.float64)
     assert np.array_equal(theta0, OM.init_params(21))
     P, Xd, Td = _t(theta0), _t(X), _t(T)
@@ -164,11 +169,15 @@ def test_select_follows_the_prediction_and_auto_is_bit_exact(gpu_lib, tmp_path):
             crd, val = _dev(T)
             ch, pred = qsd.qsd_select(model, _desc(qsd, T, sigma), [c.data_ptr() for c in crd], ws.data_ptr(),
                                       wsb, s)
-            _, _, y = OM.forward(theta, OF.features(T.crd, ext, tau, sigma)[None, :])
+            feat = OF.features(T.crd, ext, tau, sigma, T.crd[0].dtype.itemsize, 8)
+            _, _, y = OM.forward(theta, feat[None, :])
             assert np.allclose(pred, y[0], rtol=1e-4, atol=1e-4)
-            order = np.argsort(y[0])
-            if y[0][order[1]] - y[0][order[0]] > 1e-3:  # a clear winner: both sides agree
-                assert ch == 1 + int(order[0]), (pred, y)
+            valid = OF.valid_candidates(ext, tau, sigma)
+            yv = np.where(valid, y[0], np.inf)
+            order = np.argsort(yv)
+            in_range = bool(np.all((feat >= 0) & (feat <= 4)))
+            if in_range and yv[order[1]] - yv[order[0]] > 1e-3:  # a clear winner: both sides agree
+                assert ch == int(order[0]), (pred, y, valid)
             h, ch2 = qsd.qsd_plan_auto(model, _desc(qsd, T, sigma), [c.data_ptr() for c in crd], ws.data_ptr(),
                                        wsb, s)
             assert ch2 == ch

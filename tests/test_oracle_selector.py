@@ -21,7 +21,7 @@ def test_splitmix64_published_outputs():
 
 
 def test_parameter_count():
-    assert mlp.NPARAM == 32 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3 == 6467
+    assert mlp.NPARAM == 40 * 64 + 64 + 64 * 64 + 64 + 64 * 6 + 6 == 7174
 
 
 def _rand_theta(seed, scale=0.3):
@@ -30,8 +30,9 @@ def _rand_theta(seed, scale=0.3):
 
 def test_gradient_matches_central_differences():
     rng = np.random.default_rng(1)
-    X = rng.normal(size=(5, 32))
-    T = rng.normal(size=(5, 3))
+    X = rng.normal(size=(5, 40))
+    T = rng.normal(size=(5, 6))
+    T[rng.uniform(size=T.shape) < 0.3] = np.nan  # missing targets are part of the loss' definition
     theta = _rand_theta(2)
     L, g = mlp.backward(theta, X, T)
     assert abs(L - mlp.loss(theta, X, T)) < 1e-12
@@ -49,11 +50,11 @@ def test_gradient_matches_central_differences():
 def test_zero_weights_output_last_bias():
     theta = np.zeros(mlp.NPARAM)
     p = mlp.unpack(theta)
-    p["b3"][:] = [1.5, -2.0, 0.25]
+    p["b3"][:] = [1.5, -2.0, 0.25, 7.0, 0.0, -0.5]
     theta = mlp.pack(p)
-    X = np.random.default_rng(3).normal(size=(4, 32))
+    X = np.random.default_rng(3).normal(size=(4, 40))
     _, _, y = mlp.forward(theta, X)
-    assert np.array_equal(y, np.tile([1.5, -2.0, 0.25], (4, 1)))
+    assert np.array_equal(y, np.tile([1.5, -2.0, 0.25, 7.0, 0.0, -0.5], (4, 1)))
 
 
 def test_single_path_network_by_hand():
@@ -66,7 +67,7 @@ def test_single_path_network_by_hand():
     p["W3"][0, 0] = 2.0
     p["b3"][0] = -1.0
     theta = mlp.pack(p)
-    X = np.zeros((3, 32))
+    X = np.zeros((3, 40))
     X[:, 0] = [0.0, 2.0, 4.0]
     _, _, y = mlp.forward(theta, X)
     assert np.allclose(y[:, 0], [2 * 0.5 - 1, 2 * (3 * 1 + 0.5) - 1, 2 * (3 * 3 + 0.5) - 1])
@@ -83,22 +84,40 @@ def test_training_at_zero_loss_leaves_parameters():
     # to b3 give zero error, zero gradient everywhere, and Adam must not move
     p = mlp.unpack(_rand_theta(4))
     p["W3"][:] = 0.0
-    p["b3"][:] = [0.5, -1.0, 2.0]
+    p["b3"][:] = [0.5, -1.0, 2.0, 0.0, 1.0, 3.0]
     theta = mlp.pack(p)
-    X = np.random.default_rng(5).normal(size=(10, 32))
-    y = np.tile([0.5, -1.0, 2.0], (10, 1))
+    X = np.random.default_rng(5).normal(size=(10, 40))
+    y = np.tile([0.5, -1.0, 2.0, 0.0, 1.0, 3.0], (10, 1))
+    y[::3, 4] = np.nan  # a missing target adds nothing
     out, last = mlp.train(theta, X, y, epochs=3, batch=4, lr=0.1, seed=9)
     assert last == 0.0 and np.array_equal(out, theta)
 
 
 def test_training_reduces_loss_on_a_learnable_target():
     rng = np.random.default_rng(6)
-    X = rng.uniform(0, 1, size=(64, 32))
-    T = np.stack([X[:, 0] + X[:, 1], 2 * X[:, 2], -X[:, 3]], axis=1)
+    X = rng.uniform(0, 1, size=(64, 40))
+    T = np.stack([X[:, 0] + X[:, 1], 2 * X[:, 2], -X[:, 3], X[:, 4], X[:, 5] * 0.5, -X[:, 6]], axis=1)
     theta = mlp.init_params(11)
     before = mlp.loss(theta, X, T)
     theta2, _ = mlp.train(theta, X, T, epochs=60, batch=16, lr=3e-3, seed=12)
     assert mlp.loss(theta2, X, T) < 0.05 * before
+
+
+def test_missing_targets_contribute_nothing():
+    # a NaN target is equivalent to a target equal to the prediction: same loss, same gradient
+    rng = np.random.default_rng(13)
+    X = rng.normal(size=(6, 40))
+    theta = _rand_theta(14)
+    _, _, y = mlp.forward(theta, X)
+    T = rng.normal(size=(6, 6))
+    miss = rng.uniform(size=T.shape) < 0.4
+    Tn = np.where(miss, np.nan, T)
+    Ty = np.where(miss, y, T)
+    Ln, gn = mlp.backward(theta, X, Tn)
+    Ly, gy = mlp.backward(theta, X, Ty)
+    assert abs(Ln - Ly) < 1e-12 and np.allclose(gn, gy, rtol=0, atol=1e-12)
+    # and the mean still divides by all rows x outputs
+    assert abs(Ln - np.sum(np.where(miss, 0, (y - T) ** 2)) / 36) < 1e-12
 
 
 def test_epoch_order_is_a_permutation_and_uniformish():
@@ -178,16 +197,26 @@ def test_feature_counts_closed_forms():
 
 
 def test_plan_terms_on_the_paper_examples():
-    # (4,1,2,3) needs one plain pass on mode 4; (4,3,2,1) three plain passes (Sec. 3.4)
-    t = F.plan_terms([8, 8, 8, 8], (0, 1, 2, 3), (3, 0, 1, 2))
-    assert (t["s1_plain_calls"], t["s1_bucket_calls"], t["s1_plain_bits"]) == (1, 0, 3)
-    t = F.plan_terms([8, 8, 8, 8], (0, 1, 2, 3), (3, 2, 1, 0))
-    assert (t["s1_plain_calls"], t["s1_bucket_calls"], t["s1_plain_bits"]) == (3, 0, 9)
-    assert t["s3_bits"] == 12
-    # (0,2,1) from (0,1,2): one bucketed pass on mode 2 keeping mode 0
-    t = F.plan_terms([4, 16, 256], (0, 1, 2), (0, 2, 1))
-    assert (t["s1_bucket_calls"], t["s1_bucket_bits"], t["prefix1"]) == (1, 8, (0,))
-    assert t["prefix2"] == (0,) and t["s2_bucket_bits"] == 8 + 4  # K = 1: sort (2, 1) per bucket
+    # (4,1,2,3) needs one plain pass on mode 4 (Sec. 3.4): one global group of 3 bits -> 1 digit
+    # pass; Top-1 and Top-2 plan the same (their targets are sigma itself and no tail is left to
+    # sort); Top-3 is not a candidate for 4 modes; LSD sorts all 12 bits in 2 passes
+    terms, Q = F.plan_terms([8, 8, 8, 8], (0, 1, 2, 3), (3, 0, 1, 2))
+    assert terms == [(1, 0), None, (1, 0), (1, 0), None, (2, 0)]
+    assert Q == [(), (3,), (3, 0), ()]
+    # (4,3,2,1): three plain calls, one group of 9 key bits -> 2 passes
+    terms, _ = F.plan_terms([8, 8, 8, 8], (0, 1, 2, 3), (3, 2, 1, 0))
+    assert terms[0] == (2, 0) and terms[1] is None and terms[5] == (2, 0)
+    # (0,2,1) from (0,1,2) with 2/4/8-bit modes: one bucketed call on mode 2 keeping mode 0.  It
+    # packs, and flattened to (0,2) it needs 2 passes against 1, so candidate 0 runs it as a global
+    # sort; candidate 1 keeps its 8-bit bucket sort; Top-1's target is the input order and its
+    # tail group is the same bucketed sort
+    terms, Q = F.plan_terms([4, 16, 256], (0, 1, 2), (0, 2, 1))
+    assert terms == [(2, 0), (0, 8), (2, 0), None, None, (2, 0)]
+    assert Q == [(0,), (0,), (), ()]
+    # a prefix too wide to flatten (3 more passes) keeps the bucket sort in candidate 0 too, and
+    # candidate 1 then plans nothing different
+    terms, _ = F.plan_terms([1 << 20, 1 << 17, 1 << 10, 64], (0, 1, 2, 3), (0, 1, 3, 2))
+    assert terms[0] == (0, 6) and terms[1] is None
 
 
 def test_features_identity_and_ranges():
@@ -197,9 +226,9 @@ def test_features_identity_and_ranges():
            rng.integers(0, 1000, n).astype(np.int32)]
     for sigma in itertools.permutations(range(3)):
         f = F.features(crd, (100, 9, 1000), (0, 1, 2), sigma)
-        assert f.shape == (32,) and np.all(np.isfinite(f)) and np.all(f >= 0)
+        assert f.shape == (40,) and np.all(np.isfinite(f)) and np.all(f >= 0) and np.all(f <= 4)
         if sigma == (0, 1, 2):
-            assert f[22] == f[23] == f[24] == f[25] == 0
+            assert f[24] == f[25] == 0  # the minimal plan sorts nothing
 
 
 def _mix64_int(z):
@@ -211,15 +240,15 @@ def _mix64_int(z):
 
 
 def test_features_against_hand_derived_golden():
-    """All 32 features of a 6-nonzero 3-mode tensor with sigma = (0, 2, 1), whose slots are not
+    """All 40 features of a 6-nonzero 3-mode tensor with sigma = (0, 2, 1), whose slots are not
     in mode order, against values derived by hand from the feature definitions."""
     from conftest import read_golden
     g = read_golden("features_3mode.txt")
-    want = np.array([float(g[str(i)][0]) for i in range(32)])
+    want = np.array([float(g[str(i)][0]) for i in range(40)])
     nz = [(0, 1, 1), (0, 1, 4), (1, 1, 0), (1, 1, 3), (1, 2, 0), (3, 2, 2)]
     crd = [np.array([t[m] for t in nz], dtype=np.int32) for m in range(3)]
     # the derivation's premise: values 0..4 share no bitmap bit and no bucket
     h = [_mix64_int(v) for v in range(5)]
     assert len({x & 0xFFFF for x in h}) == 5 and len({(x >> 16) & 1023 for x in h}) == 5
-    f = F.features(crd, (9, 3, 20), (0, 1, 2), (0, 2, 1))
+    f = F.features(crd, (9, 3, 20), (0, 1, 2), (0, 2, 1), crd_bytes=4, val_bytes=8)
     np.testing.assert_allclose(f, want, rtol=1e-12, atol=0)
