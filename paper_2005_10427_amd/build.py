@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqsd.so")
 
 SOURCES = ["api.cpp", "plan.cpp", "select.cpp", "kernels.hip", "select_kernels.hip", "digit_u32_u64.hip",
-           "digit_u32_u32.hip", "digit_u64_u64.hip", "digit_u64_u32.hip", "noalloc.hip"]
+           "digit_u32_u32.hip", "digit_u64_u64.hip", "digit_u64_u32.hip", "noalloc.hip", "csf_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

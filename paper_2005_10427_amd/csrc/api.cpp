@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "csf_kernels.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -753,11 +754,10 @@ qsd_status qsd_pack_csf(qsd_plan_t plan, int64_t nnz, const void* const* sorted_
         return QSD_OK;
     }
     CsfArgs ca{};
-    for (int m = 0; m < p.r; ++m) {
-        ca.crd[m] = sorted_crd[m];
-        ca.sigma[m] = p.out_order[m];
-        ca.pos[m] = pos[m];
-        ca.out_crd[m] = crd[m];
+    for (int d = 0; d < p.r; ++d) {
+        ca.crd[d] = sorted_crd[p.out_order[d]];  // level d + 1 holds mode sigma_{d+1}
+        ca.pos[d] = pos[d];
+        ca.out_crd[d] = crd[d];
     }
     ca.r = p.r;
     ca.n = n;

@@ -232,43 +232,7 @@ struct ValidateArgs {
     uint32_t* flags;            // bit 0: out of range, bit 1: unsorted
 };
 
-constexpr int kCsfTile = 2048;     // records per tile of the CSF pack
-
-struct CsfArgs {
-    const void* crd[8];         // sorted coordinates, original mode order
-    int32_t r;
-    int32_t sigma[8];
-    uint32_t n;
-    void* pos[8];
-    void* out_crd[8];
-    int64_t* fiber_counts;
-    uint32_t* status;           // (r-1) words per tile, zeroed beforehand
-    uint32_t* tile_counter;
-    uint32_t* err;
-};
-
-// Expansion of a CSF tensor (the layout qsd_pack_csf writes) to coordinate arrays, level by
-// level.  Level d (1-based) holds F_d fibers; pos[d-1] has F_{d-1} + 1 entries (the children
-// of level-(d-1) fiber p are level-d fibers pos[d-1][p] .. pos[d-1][p+1]-1), crd[d-1] has F_d.
-// F_0 = 1 and F_d = pos[d-1][F_{d-1}], so every count is read from the arrays themselves.
-struct CsfExpandArgs {
-    const void* pos[8];
-    const void* crd[8];
-    int32_t r;
-    int32_t level;              // d: the level this launch expands (1 <= d < r)
-    uint32_t n;                 // leaves
-    uint8_t* flags;             // n bytes: 1 where a leaf is the first leaf of a level-d fiber
-    uint32_t* status;           // one word per tile of kBoundTile leaves, zeroed beforehand
-    uint32_t* tile_counter;
-    void* out;                  // the level's coordinate of every leaf
-    uint32_t* err;
-};
-
 hipError_t launch_zero(const ZeroArgs& a, hipStream_t s);
-// flags[first leaf of every level-d fiber] = 1 (flags zeroed beforehand)
-hipError_t launch_csf_mark(const CsfExpandArgs& a, int crd_bytes, hipStream_t s);
-// out[j] = crd[d-1][number of flags at or before j, minus 1]
-hipError_t launch_csf_expand(const CsfExpandArgs& a, int crd_bytes, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_hist(const HistArgs& a, int r, int crd_bytes, int grid, hipStream_t s);
 hipError_t launch_digit(const DigitArgs& a, int r, int crd_bytes, int val_bytes, int items, hipStream_t s);
@@ -284,7 +248,6 @@ hipError_t launch_classify(const ClassArgs& a, uint32_t max_segments, hipStream_
 hipError_t launch_small(const SmallArgs& a, int crd_bytes, int val_bytes, uint32_t max_items,
                         hipStream_t s);
 hipError_t launch_validate(const ValidateArgs& a, int crd_bytes, hipStream_t s);
-hipError_t launch_csf(const CsfArgs& a, int crd_bytes, hipStream_t s);
 
 int device_cu_count();
 

@@ -187,38 +187,4 @@ hipError_t launch_validate(const ValidateArgs& a, int crd_bytes, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t launch_csf_mark(const CsfExpandArgs& a, int crd_bytes, hipStream_t s) {
-    const uint32_t grid = (uint32_t)std::max<uint64_t>(
-        1, std::min<uint64_t>((a.n + kBlock - 1) / kBlock, (uint64_t)device_cu_count() * 8));
-    if (crd_bytes == 8)
-        hipLaunchKernelGGL(k_csf_mark<uint64_t>, dim3(grid), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_csf_mark<uint32_t>, dim3(grid), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_csf_expand(const CsfExpandArgs& a, int crd_bytes, hipStream_t s) {
-    const uint32_t grid = (a.n + kBoundTile - 1) / kBoundTile;
-    if (!grid) return hipSuccess;
-    if (crd_bytes == 8)
-        hipLaunchKernelGGL(k_csf_expand<uint64_t>, dim3(grid), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_csf_expand<uint32_t>, dim3(grid), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_csf(const CsfArgs& a, int crd_bytes, hipStream_t s) {
-    const uint32_t tiles = (a.n + kCsfTile - 1) / kCsfTile;
-    if (!tiles) return hipSuccess;
-    static int res32 = 0, res64 = 0;  // resident workgroups of the persistent kernel
-    if (crd_bytes == 8) {
-        if (!res64) res64 = resident_blocks(k_csf<uint64_t, int64_t>);
-        hipLaunchKernelGGL((k_csf<uint64_t, int64_t>), dim3(std::min<uint32_t>(tiles, res64)), dim3(kBlock), 0, s, a);
-    } else {
-        if (!res32) res32 = resident_blocks(k_csf<uint32_t, int32_t>);
-        hipLaunchKernelGGL((k_csf<uint32_t, int32_t>), dim3(std::min<uint32_t>(tiles, res32)), dim3(kBlock), 0, s, a);
-    }
-    return hipGetLastError();
-}
-
 }  // namespace qsd

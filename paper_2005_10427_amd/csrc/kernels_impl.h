@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace qsd {
 namespace {
@@ -66,6 +67,15 @@ __device__ __forceinline__ void count_slot(uint32_t* s_h, uint32_t slot, int lan
         const uint32_t run = after ? (uint32_t)__builtin_ctzll(after) + 1u : 64u - lane;
         atomicAdd(&s_h[slot], run);
     }
+}
+// Uniform values read from LDS into scalar registers.
+__device__ __forceinline__ uint32_t uni32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    return ((uint64_t)uni32((uint32_t)(v >> 32)) << 32) | uni32((uint32_t)v);
+}
+template <typename P>
+__device__ __forceinline__ P* uni_ptr(P* p) {
+    return reinterpret_cast<P*>(uni64(reinterpret_cast<uint64_t>(p)));
 }
 // number of set bits of m in lanes below this one
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
@@ -165,48 +175,89 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a) {
     const int npass = a.npass;
     const int words = npass * kBins;
     for (int i = tid; i < words; i += kBlock) s_h[i] = 0;
-    // per-pass shift and mask, uniform: kept in scalar registers for the whole kernel
-    uint32_t plo[MAXP], pmask[MAXP];
-#pragma unroll
-    for (int p = 0; p < MAXP; ++p) {
-        plo[p] = p < npass ? (uint32_t)a.lo[p] : 0u;
-        pmask[p] = p < npass ? (1u << a.bits[p]) - 1u : 0u;
-    }
     const uint32_t spare = MAXP * kBins;  // items past the end count into the spare block
+    uint32_t kw[R];  // width of each key field
+#pragma unroll
+    for (int m = 0; m < R; ++m) kw[m] = a.key.mask[m] ? 64u - (uint32_t)__builtin_clzll(a.key.mask[m]) : 0u;
 
-    // count the digits of records [lo, hi) with U loads per key mode in flight
-    auto count_range = [&](uint32_t lo, uint32_t hi) {
-        for (uint32_t base = lo; base < hi; base += kBlock * U) {
-            uint64_t key[U];
+    // count the digits of records [lo, hi) with U loads per key mode in flight.  The key is
+    // built in two 32-bit halves; a pass's digit is one funnel shift (or one shift above bit
+    // 31) and one and-or that also adds the pass's block offset.  Whether a pass's digits come
+    // in runs is decided once per round from its first record (a wave where at least half of
+    // the lanes start a run counts every lane directly); both ways count every lane once.
+    // One round: U records per thread.  FULL rounds (every record below hi, all but the last)
+    // need no range checks.
+    auto round = [&](uint32_t base, uint32_t hi, auto full) __attribute__((always_inline)) {
+        constexpr bool FULL = decltype(full)::value;
+        uint32_t klo[U], khi[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) key[u] = 0;
+        for (int u = 0; u < U; ++u) klo[u] = khi[u] = 0;
 #pragma unroll
-            for (int m = 0; m < R; ++m) {
-                if (!a.key.mask[m]) continue;
-                const CT* src = (const CT*)a.crd[m];
-                CT c[U];
+        for (int m = 0; m < R; ++m) {
+            if (!a.key.mask[m]) continue;
+            const CT* src = (const CT*)a.crd[m];
+            CT c[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const uint32_t e = base + u * kBlock + tid;
-                    c[u] = e < hi ? src[e] : CT(0);
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    key[u] |= (((uint64_t)c[u] >> a.key.src_lo[m]) & a.key.mask[m]) << a.key.dst[m];
+            for (int u = 0; u < U; ++u) {
+                const uint32_t e = base + u * kBlock + tid;
+                c[u] = (FULL || e < hi) ? src[e] : CT(0);
             }
-            bool ok[U];  // records past the end count into the spare block
+            const uint32_t sl = a.key.src_lo[m], ds = a.key.dst[m];
+            if (sizeof(CT) == 4 && ds >= 32) {
+                // 32-bit coordinates: the field lands in one half unless it straddles bit 32
 #pragma unroll
-            for (int u = 0; u < U; ++u) ok[u] = base + u * kBlock + tid < hi;
+                for (int u = 0; u < U; ++u) khi[u] |= (((uint32_t)c[u] >> sl) & (uint32_t)a.key.mask[m]) << (ds - 32);
+            } else if (sizeof(CT) == 4 && ds + kw[m] <= 32) {
 #pragma unroll
-            for (int p = 0; p < MAXP; ++p) {
-                if (p >= npass) break;
+                for (int u = 0; u < U; ++u) klo[u] |= (((uint32_t)c[u] >> sl) & (uint32_t)a.key.mask[m]) << ds;
+            } else {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t slot = ok[u] ? p * kBins + ((uint32_t)(key[u] >> plo[p]) & pmask[p]) : spare;
-                    count_slot(s_h, slot, lane);
+                    const uint64_t f = (((uint64_t)c[u] >> sl) & a.key.mask[m]) << ds;
+                    klo[u] |= (uint32_t)f;
+                    khi[u] |= (uint32_t)(f >> 32);
                 }
             }
         }
+        bool ok[U];  // records past the end count into the spare block
+#pragma unroll
+        for (int u = 0; u < U; ++u) ok[u] = FULL || base + u * kBlock + tid < hi;
+        // one copy of the pass loop (its shift and mask are scalar loads of the arguments)
+#pragma unroll 1
+        for (int p = 0; p < npass; ++p) {
+            const uint32_t plo = (uint32_t)a.lo[p], pmask = (1u << a.bits[p]) - 1u;
+            uint32_t slot[U];
+            if (plo >= 32) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) slot[u] = khi[u] >> (plo - 32);
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) slot[u] = __builtin_amdgcn_alignbit(khi[u], klo[u], plo);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t v = (slot[u] & pmask) | (uint32_t)(p * kBins);
+                slot[u] = (FULL || ok[u]) ? v : spare;
+            }
+            // lane 0 always starts a run: the value "below" it is ~0, which no slot equals
+            if (__popcll(ballot(from_lane_below(slot[0]) != slot[0])) >= 32) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) atomicAdd(&s_h[slot[u]], 1u);
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) count_slot(s_h, slot[u], lane);
+            }
+        }
+    };
+    // count the digits of records [lo, hi) with U loads per key mode in flight.  The key is
+    // built in two 32-bit halves; a pass's digit is one funnel shift (or one shift above bit
+    // 31) and one and-or that also adds the pass's block offset.  Whether a pass's digits come
+    // in runs is decided once per round from its first record (a wave where at least half of
+    // the lanes start a run counts every lane directly); both ways count every lane once.
+    auto count_range = [&](uint32_t lo, uint32_t hi) __attribute__((always_inline)) {
+        uint32_t base = lo;
+        for (; base + kBlock * U <= hi; base += kBlock * U) round(base, hi, std::true_type{});
+        if (base < hi) round(base, hi, std::false_type{});
     };
     __syncthreads();
     if (!a.seg_mode) {
@@ -427,20 +478,25 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
     __shared__ uint32_t s_tmp[2 * kWaves];
     __shared__ uint32_t s_geo[6];                // tile, start, len, segment base, k, first tile
     __shared__ uint32_t s_hpre[kBins];           // one segment: exclusive prefix of the digit counts
+    // batch mode: the table entry of the tile's tensor, copied once per tile
+    __shared__ uint32_t s_bp[MODE == 2 ? sizeof(BatchPass) / 4 : 1];
+    static_assert(sizeof(BatchPass) % 4 == 0, "the table entry is copied in 32-bit words");
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (MODE == 0) s_hpre[tid] = block_excl_scan(a.hist[tid], s_tmp, nullptr);  // same for every tile
 
     for (;;) {
-        if (tid == 0) {
+        if (tid < 64) {
             // global and batch modes: queue q (of G) hands out chunks q, q + G, q + 2G, ... of
             // kTileChunk consecutive (launch) tiles.  Every queue has a workgroup (G <= grid),
             // each queue's tiles go out in increasing order, and a tile waits only for lower
             // tiles, so the lowest unfinished tile always has a running workgroup or a free one
-            // that will take it.
+            // that will take it.  Wave 0 computes the geometry (lane 0 takes the tile).
             const uint32_t G = (MODE != 1 && a.ntiles >= kQueueMinTiles) ? min(kTileQueues, gridDim.x) : 1u;
             const uint32_t qi = blockIdx.x % G;
-            const uint32_t lt = atomicAdd(a.tile_counter + qi, 1u);
+            uint32_t taken = 0;
+            if (tid == 0) taken = atomicAdd(a.tile_counter + qi, 1u);
+            const uint32_t lt = uni32(taken);
             uint32_t t = lt, ntiles = a.ntiles, start = 0, len = 0, base = 0, k = 0, lowest = 0;
             bool live = false;
             if (MODE == 1) {
@@ -466,6 +522,9 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                     len = g.w;
                     lowest = t - start / TILE;  // the tensor's first tile
                     live = true;
+                    // the tensor's table entry, read by the whole wave at once
+                    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.batch + k);
+                    for (int i = tid; i < (int)(sizeof(BatchPass) / 4); i += 64) s_bp[i] = src[i];
                 }
             } else {
                 t = ((lt / kTileChunk) * G + qi) * kTileChunk + lt % kTileChunk;
@@ -475,12 +534,14 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
                     live = true;
                 }
             }
-            s_geo[0] = live ? t : 0xFFFFFFFFu;
-            s_geo[1] = start;
-            s_geo[2] = len;
-            s_geo[3] = base;
-            s_geo[4] = k;
-            s_geo[5] = lowest;
+            if (tid == 0) {
+                s_geo[0] = live ? t : 0xFFFFFFFFu;
+                s_geo[1] = start;
+                s_geo[2] = len;
+                s_geo[3] = base;
+                s_geo[4] = k;
+                s_geo[5] = lowest;
+            }
         }
         __syncthreads();
         // tile geometry is uniform: keep it in scalar registers
@@ -492,18 +553,32 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
         const uint32_t k = __builtin_amdgcn_readfirstlane(s_geo[4]);
         const uint32_t lowest = __builtin_amdgcn_readfirstlane(s_geo[5]);
         const bool first = (t == lowest);
-        const BatchPass* J = a.batch + k;  // batch mode only
-        const DevKey& key = MODE == 2 ? J->key : a.key;
-        const int lo_bit = MODE == 2 ? J->lo : a.lo;
-        const int nbits = MODE == 2 ? J->bits : a.bits;
-        const int r = MODE == 2 ? J->r : R;
-        const void* const* src_crd = MODE == 2 ? J->src_crd : a.src_crd;
-        void* const* dst_crd = MODE == 2 ? J->dst_crd : a.dst_crd;
-        const void* src_val = MODE == 2 ? J->src_val : a.src_val;
-        void* dst_val = MODE == 2 ? J->dst_val : a.dst_val;
-        const uint32_t* hist = MODE == 2 ? J->hist : a.hist + (size_t)k * a.hist_stride;
-        const int32_t* pk_pos = MODE == 2 ? J->pk_pos : a.pk_pos;
-        const uint64_t* pk_mask = MODE == 2 ? J->pk_mask : a.pk_mask;
+        // the pass's parameters.  Batch mode reads the tensor's table entry from its LDS copy
+        // into scalar registers once per tile: read from global memory, each use would be
+        // reloaded after every store, since the compiler cannot tell that the stores leave the
+        // table alone.
+        const BatchPass& J = *reinterpret_cast<const BatchPass*>(s_bp);
+        DevKey key;
+        const void* src_crd[R];
+        void* dst_crd[R];
+        int32_t pk_pos[R];
+        uint64_t pk_mask[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            key.mask[m] = MODE == 2 ? uni64(J.key.mask[m]) : a.key.mask[m];
+            key.src_lo[m] = MODE == 2 ? (int32_t)uni32((uint32_t)J.key.src_lo[m]) : a.key.src_lo[m];
+            key.dst[m] = MODE == 2 ? (int32_t)uni32((uint32_t)J.key.dst[m]) : a.key.dst[m];
+            src_crd[m] = MODE == 2 ? uni_ptr(J.src_crd[m]) : a.src_crd[m];
+            dst_crd[m] = MODE == 2 ? uni_ptr(J.dst_crd[m]) : a.dst_crd[m];
+            pk_pos[m] = MODE == 2 ? (int32_t)uni32((uint32_t)J.pk_pos[m]) : a.pk_pos[m];
+            pk_mask[m] = MODE == 2 ? uni64(J.pk_mask[m]) : a.pk_mask[m];
+        }
+        const int lo_bit = MODE == 2 ? (int)uni32((uint32_t)J.lo) : a.lo;
+        const int nbits = MODE == 2 ? (int)uni32((uint32_t)J.bits) : a.bits;
+        const int r = MODE == 2 ? (int)uni32((uint32_t)J.r) : R;
+        const void* src_val = MODE == 2 ? uni_ptr(J.src_val) : a.src_val;
+        void* dst_val = MODE == 2 ? uni_ptr(J.dst_val) : a.dst_val;
+        const uint32_t* hist = MODE == 2 ? uni_ptr(J.hist) : a.hist + (size_t)k * a.hist_stride;
         const uint32_t dmask = (1u << nbits) - 1u;
         const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;  // wave w owns a contiguous slice
 
@@ -711,87 +786,6 @@ __global__ void __launch_bounds__(256) k_digit(DigitArgs a) {
 template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_digit3(DigitArgs a) {
     digit_body<R, CT, VT, ITEMS, MODE, PK>(a);
-}
-
-// ------------------------------------------------------------------------------ CSF expansion
-
-// F_d of a CSF tensor: F_0 = 1 and F_e = pos[e-1][F_{e-1}].
-template <typename PT>
-__device__ __forceinline__ uint64_t csf_fibers(const CsfExpandArgs& a, int d) {
-    uint64_t f = 1;
-    for (int e = 1; e <= d; ++e) f = (uint64_t)((const PT*)a.pos[e - 1])[f];
-    return f;
-}
-
-// Every level-d fiber marks its first leaf: following the first child down from level d to the
-// leaves, x <- pos[e][x] for e = d .. r-1.  Leaf indices are clamped into [0, n) so that a
-// malformed tensor cannot write outside the flags.
-template <typename PT>
-__global__ void __launch_bounds__(256) k_csf_mark(CsfExpandArgs a) {
-    uint64_t Fe[9];  // fiber counts of every level, each index below clamped to its array
-    Fe[0] = 1;
-    for (int e = 1; e <= a.r; ++e) Fe[e] = (uint64_t)((const PT*)a.pos[e - 1])[Fe[e - 1]];
-    const uint64_t F = Fe[a.level];
-    for (uint64_t f = blockIdx.x * (uint64_t)kBlock + threadIdx.x; f < F; f += gridDim.x * (uint64_t)kBlock) {
-        uint64_t x = f;
-        for (int e = a.level; e < a.r; ++e) x = (uint64_t)((const PT*)a.pos[e])[min(x, Fe[e])];
-        if (x < a.n) a.flags[x] = 1;
-    }
-}
-
-// The level-d coordinate of every leaf: its level-d ancestor is the number of fibers whose first
-// leaf is at or before it, minus one (an inclusive count of the flags, tiles chained by a
-// one-word decoupled look-back), and the coordinate is that fiber's entry of crd[d-1].
-template <typename CT>
-__global__ void __launch_bounds__(256) k_csf_expand(CsfExpandArgs a) {
-    constexpr int ITEMS = kBoundTile / kBlock;
-    __shared__ uint32_t s_wsum[kWaves];
-    __shared__ uint32_t s_geo[2];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) s_geo[0] = atomicAdd(a.tile_counter, 1u);
-    __syncthreads();
-    const uint32_t t = s_geo[0];
-    const uint32_t start = t * kBoundTile;
-    if (start >= a.n) return;
-    const uint32_t len = min((uint32_t)kBoundTile, a.n - start);
-    const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
-    uint64_t flags[ITEMS];
-    uint32_t wcount = 0;
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t off = wb + i * 64;
-        flags[i] = ballot(off < len && a.flags[start + off] != 0);
-        wcount += (uint32_t)__popcll(flags[i]);
-    }
-    if (lane == 0) s_wsum[wave] = wcount;
-    __syncthreads();
-    if (wave == 0) {
-        uint32_t tot = 0;
-        for (int w = 0; w < kWaves; ++w) tot += s_wsum[w];
-        uint32_t* st = a.status + t;
-        if (lane == 0) st_status(st, (t == 0 ? kFlagP : kFlagA) | tot);
-        const uint32_t excl = t == 0 ? 0u : wave_look_back(a.status, t, 1, 0, 0, a.err);
-        if (lane == 0) {
-            if (t != 0) st_status(st, kFlagP | (excl + tot));
-            s_geo[1] = excl;
-        }
-    }
-    __syncthreads();
-    uint32_t pos = s_geo[1];
-    for (int w = 0; w < wave; ++w) pos += s_wsum[w];
-    const CT* crd = (const CT*)a.crd[a.level - 1];
-    const uint64_t F = csf_fibers<CT>(a, a.level);
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint64_t f = flags[i];
-        const uint32_t off = wb + i * 64;
-        const uint32_t incl = pos + lanes_below(f) + (uint32_t)((f >> lane) & 1ull);  // flags at or before
-        if (off < len) {
-            const uint64_t anc = incl ? min((uint64_t)incl - 1, F ? F - 1 : 0) : 0;
-            ((CT*)a.out)[start + off] = crd[anc];
-        }
-        pos += (uint32_t)__popcll(f);
-    }
 }
 
 // ------------------------------------------------------------------------------ buckets
@@ -1160,6 +1154,7 @@ template <int R, typename CT>
 __global__ void __launch_bounds__(256) k_hist_batch(BatchHistArgs a) {
     constexpr int U = kHistU, MAXP = 16;
     __shared__ uint32_t s_h[MAXP * kBins + kBins];  // + a spare block for items past the end
+    __shared__ uint32_t s_pass[3][MAXP];            // per pass of the current tensor: lo, mask, sub-key
     const int tid = threadIdx.x, lane = tid & 63;
     const uint32_t spare = MAXP * kBins;
     for (int i = tid; i < MAXP * kBins; i += kBlock) s_h[i] = 0;
@@ -1168,7 +1163,6 @@ __global__ void __launch_bounds__(256) k_hist_batch(BatchHistArgs a) {
     uint32_t cur = 0xFFFFFFFFu, n = 0, tile0 = 0;
     int npass = 0, nsub = 1, words = 0;
     uint32_t* hist = nullptr;
-    uint32_t plo[MAXP], pmask[MAXP], psub[MAXP];
     uint64_t km[2][R];
     uint32_t ks[2][R], kd[2][R];
     const CT* src[R];
@@ -1178,6 +1172,76 @@ __global__ void __launch_bounds__(256) k_hist_batch(BatchHistArgs a) {
             const uint32_t c = s_h[i];
             if (c) atomicAdd(&hist[i], c);
             s_h[i] = 0;
+        }
+    };
+    // One round of U records per thread: the key (one or two 64-bit sub-keys) as 32-bit halves,
+    // then each pass's digit by one funnel shift; the run aggregation of consecutive lanes is
+    // skipped for a pass whose first record of the round starts a run in at least half of the
+    // lanes (unsorted digits), and either way every lane is counted once.
+    auto round = [&](uint32_t base, uint32_t end) __attribute__((always_inline)) {
+        uint32_t k[2][2][U];  // [sub-key][half][u]
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) k[q][0][u] = k[q][1][u] = 0;
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            if (!(km[0][m] | km[1][m])) continue;
+            // the index is clamped to the tensor's last record instead of branching, so the U
+            // loads are issued back to back; records past the end are counted into the spare
+            // block below whatever their value
+            CT c[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t e = base + u * kBlock + tid;
+                c[u] = src[m][min(e, end - 1u)];
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                if (q >= nsub) break;  // keys wider than 64 bits only
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint64_t f = (((uint64_t)c[u] >> ks[q][m]) & km[q][m]) << kd[q][m];
+                    k[q][0][u] |= (uint32_t)f;
+                    k[q][1][u] |= (uint32_t)(f >> 32);
+                }
+            }
+        }
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) ok[u] = base + u * kBlock + tid < end;
+#pragma unroll 1
+        for (int p = 0; p < npass; ++p) {
+            const uint32_t plo = uni32(s_pass[0][p]), pmask = uni32(s_pass[1][p]);
+            const bool hi_sub = uni32(s_pass[2][p]) != 0;
+            uint32_t slot[U];
+            if (hi_sub) {
+                if (plo >= 32) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) slot[u] = k[1][1][u] >> (plo - 32);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) slot[u] = __builtin_amdgcn_alignbit(k[1][1][u], k[1][0][u], plo);
+                }
+            } else {
+                if (plo >= 32) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) slot[u] = k[0][1][u] >> (plo - 32);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) slot[u] = __builtin_amdgcn_alignbit(k[0][1][u], k[0][0][u], plo);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) slot[u] = ok[u] ? ((slot[u] & pmask) | (uint32_t)(p * kBins)) : spare;
+            // lane 0 always starts a run: the value "below" it is ~0, which no slot equals
+            if (__popcll(ballot(from_lane_below(slot[0]) != slot[0])) >= 32) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) atomicAdd(&s_h[slot[u]], 1u);
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) count_slot(s_h, slot[u], lane);
+            }
         }
     };
     __syncthreads();
@@ -1194,70 +1258,29 @@ __global__ void __launch_bounds__(256) k_hist_batch(BatchHistArgs a) {
             hist = J.hist;
             words = npass * kBins;
             const int r = J.r;
-#pragma unroll
-            for (int p = 0; p < MAXP; ++p) {
-                plo[p] = p < npass ? (uint32_t)J.lo[p] : 0u;
-                pmask[p] = p < npass ? (1u << J.bits[p]) - 1u : 0u;
-                psub[p] = p < npass ? (uint32_t)J.sub[p] : 0u;
+            if (tid < MAXP) {
+                const bool on = tid < npass;
+                s_pass[0][tid] = on ? (uint32_t)J.lo[tid] : 0u;
+                s_pass[1][tid] = on ? (1u << J.bits[tid]) - 1u : 0u;
+                s_pass[2][tid] = on ? (uint32_t)J.sub[tid] : 0u;
             }
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int m = 0; m < R; ++m) {
+                    // the same for every lane: held in scalar registers
                     const bool on = q < nsub && m < r;
-                    km[q][m] = on ? J.key[q].mask[m] : 0ull;
-                    ks[q][m] = on ? (uint32_t)J.key[q].src_lo[m] : 0u;
-                    kd[q][m] = on ? (uint32_t)J.key[q].dst[m] : 0u;
+                    km[q][m] = on ? uni64(J.key[q].mask[m]) : 0ull;
+                    ks[q][m] = on ? uni32((uint32_t)J.key[q].src_lo[m]) : 0u;
+                    kd[q][m] = on ? uni32((uint32_t)J.key[q].dst[m]) : 0u;
                 }
 #pragma unroll
-            for (int m = 0; m < R; ++m) src[m] = (const CT*)J.crd[m];
+            for (int m = 0; m < R; ++m) src[m] = uni_ptr((const CT*)J.crd[m]);
             __syncthreads();
         }
         const uint32_t start = (t - tile0) * a.tile;
         const uint32_t end = min(n, start + a.tile);
-        for (uint32_t base = start; base < end; base += kBlock * U) {
-            uint64_t k0[U], k1[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) k0[u] = k1[u] = 0;
-#pragma unroll
-            for (int m = 0; m < R; ++m) {
-                if (!(km[0][m] | km[1][m])) continue;
-                // the index is clamped to the tensor's last record instead of branching, so the
-                // U loads are issued back to back; records past the end are counted into the
-                // spare block below whatever their value
-                CT c[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const uint32_t e = base + u * kBlock + tid;
-                    c[u] = src[m][min(e, end - 1u)];
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) k0[u] |= (((uint64_t)c[u] >> ks[0][m]) & km[0][m]) << kd[0][m];
-                if (nsub > 1) {  // keys wider than 64 bits only
-#pragma unroll
-                    for (int u = 0; u < U; ++u) k1[u] |= (((uint64_t)c[u] >> ks[1][m]) & km[1][m]) << kd[1][m];
-                }
-            }
-#pragma unroll
-            for (int p = 0; p < MAXP; ++p) {
-                if (p >= npass) break;
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const uint32_t e = base + u * kBlock + tid;
-                    const uint64_t key = psub[p] ? k1[u] : k0[u];
-                    const uint32_t slot = e < end ? p * kBins + ((uint32_t)(key >> plo[p]) & pmask[p]) : spare;
-                    // runs of one digit in consecutive lanes are added once, from their first lane
-                    const uint32_t prev = from_lane_below(slot);
-                    const bool head = (lane == 0) || (prev != slot);
-                    const uint64_t heads = ballot(head);
-                    if (head) {
-                        const uint64_t after = (lane == 63) ? 0ull : (heads >> (lane + 1));
-                        const uint32_t run = after ? (uint32_t)__builtin_ctzll(after) + 1u : 64u - lane;
-                        atomicAdd(&s_h[slot], run);
-                    }
-                }
-            }
-        }
+        for (uint32_t base = start; base < end; base += kBlock * U) round(base, end);
         a.status_zero[(size_t)t * kBins + tid] = 0;
     }
     if (cur != 0xFFFFFFFFu) flush();
@@ -1459,132 +1482,6 @@ __global__ void __launch_bounds__(256) k_validate(ValidateArgs a) {
         }
     }
     if (bad) atomicOr(a.flags, bad);
-}
-
-// ------------------------------------------------------------------------------ CSF pack
-
-// Fiber boundaries of levels 1..r-1 (prefix sigma_1..sigma_d changes), numbered with an
-// (r-1)-word look-back; level r is the identity.  Writes crd_d and pos_d.
-template <typename CT, typename PT>
-__global__ void __launch_bounds__(256) k_csf(CsfArgs a) {
-    constexpr int ITEMS = kCsfTile / kBlock, TILE = kCsfTile;
-    __shared__ uint32_t s_wsum[8][kWaves];
-    __shared__ uint32_t s_excl[8];
-    __shared__ uint32_t s_t;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int L = a.r - 1;  // counted levels
-    // persistent: tiles in increasing order from one counter, so that every look-back ends
-    for (;;) {
-        if (tid == 0) s_t = atomicAdd(a.tile_counter, 1u);
-        __syncthreads();
-        const uint32_t t = s_t;
-        const uint32_t start = t * TILE;
-        if (start >= a.n) break;
-        const uint32_t len = min((uint32_t)TILE, a.n - start);
-        const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
-        // level of the first differing mode: records j with first-difference level <= d start
-        // a level-d fiber.  lev = 0 for the first record (every level starts).
-        uint8_t lev[ITEMS];
-        uint32_t wcnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t off = wb + i * 64;
-            // lev: first level whose mode differs from the previous record (r: none below r)
-            lev[i] = off < len ? (start + off == 0 ? 0 : (uint8_t)a.r) : 0xFF;
-        }
-        for (int d = L - 1; d >= 0; --d) {  // deepest level first, so the shallowest wins
-            const CT* p = (const CT*)a.crd[a.sigma[d]];
-            CT cur[ITEMS], prv[ITEMS];
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const uint32_t off = wb + i * 64;
-                const uint32_t e = start + off;
-                const bool ok = off < len && e > 0;
-                cur[i] = ok ? p[e] : CT(0);
-                prv[i] = ok ? p[e - 1] : CT(0);
-            }
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i)
-                if (lev[i] != 0xFF && lev[i] != 0 && cur[i] != prv[i]) lev[i] = (uint8_t)d;
-        }
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t off = wb + i * 64;
-            const int lv = lev[i];
-            for (int d = 0; d < L; ++d) wcnt[d] += (uint32_t)__popcll(ballot(off < len && lv <= d));
-        }
-        if (lane == 0)
-            for (int d = 0; d < L; ++d) s_wsum[d][wave] = wcnt[d];
-        __syncthreads();
-        // fiber numbers before this tile: one wave per level, 64 predecessors per round trip
-        for (int d = wave; d < L; d += kWaves) {
-            uint32_t tot = 0;
-            for (int w = 0; w < kWaves; ++w) tot += s_wsum[d][w];
-            uint32_t* st = a.status + (size_t)t * 8 + d;
-            uint32_t excl = 0;
-            if (t == 0) {
-                if (lane == 0) st_status(st, kFlagP | tot);
-            } else {
-                if (lane == 0) st_status(st, kFlagA | tot);
-                excl = wave_look_back(a.status, t, 8, (uint32_t)d, 0, a.err);
-                if (lane == 0) st_status(st, kFlagP | (excl + tot));
-            }
-            if (lane == 0) {
-                s_excl[d] = excl;
-                if (start + len == a.n) a.fiber_counts[d + 1] = excl + tot;
-            }
-        }
-        if (tid == 0 && start + len == a.n) {
-            a.fiber_counts[0] = 1;
-            a.fiber_counts[a.r] = a.n;
-        }
-        __syncthreads();
-        // running fiber number per level for this thread's records
-        uint32_t base[8];
-        for (int d = 0; d < L; ++d) {
-            uint32_t b = s_excl[d];
-            for (int w = 0; w < wave; ++w) b += s_wsum[d][w];
-            base[d] = b;
-        }
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t off = wb + i * 64;
-            const uint32_t e = start + off;
-            const int lv = lev[i];
-            uint32_t fid[8];
-            for (int d = 0; d < L; ++d) {
-                const uint64_t m = ballot(off < len && lv <= d);
-                fid[d] = base[d] + lanes_below(m);  // fiber number if this record starts one
-                base[d] += (uint32_t)__popcll(m);
-            }
-            if (off < len) {
-                // level d (1-based) fiber starts here when lv <= d-1; leaves always start
-                for (int d = 1; d <= a.r; ++d) {
-                    const bool starts = (d == a.r) || (lv <= d - 1);
-                    if (!starts) continue;
-                    const uint32_t f = (d == a.r) ? e : fid[d - 1];
-                    ((CT*)a.out_crd[d - 1])[f] = ((const CT*)a.crd[a.sigma[d - 1]])[e];
-                    // a new parent at level d-1 (or the root for d = 1) records its first child
-                    if (d == 1) {
-                        if (e == 0) ((PT*)a.pos[0])[0] = 0;
-                    } else if (lv <= d - 2) {
-                        ((PT*)a.pos[d - 1])[fid[d - 2]] = (PT)f;
-                    }
-                }
-            }
-        }
-        if (tid == 0 && start + len == a.n) {
-            // closing offsets: pos_d[F_{d-1}] = F_d
-            ((PT*)a.pos[0])[1] = (PT)(L >= 1 ? (s_excl[0] + s_wsum[0][0] + s_wsum[0][1] + s_wsum[0][2] + s_wsum[0][3]) : a.n);
-            for (int d = 2; d <= a.r; ++d) {
-                const uint32_t fprev = s_excl[d - 2] + s_wsum[d - 2][0] + s_wsum[d - 2][1] + s_wsum[d - 2][2] + s_wsum[d - 2][3];
-                const uint32_t fcur = (d == a.r) ? a.n
-                    : s_excl[d - 1] + s_wsum[d - 1][0] + s_wsum[d - 1][1] + s_wsum[d - 1][2] + s_wsum[d - 1][3];
-                ((PT*)a.pos[d - 1])[fprev] = (PT)fcur;
-            }
-        }
-        __syncthreads();  // s_wsum / s_excl / s_t are rewritten by the next tile
-    }
 }
 
 // ------------------------------------------------------------------------------ dispatch helpers

@@ -234,22 +234,28 @@ def test_validation_errors(gpu_lib):
     torch.cuda.synchronize()
 
 
-def test_csf_pack_matches_oracle(gpu_lib):
+@pytest.mark.parametrize("crd_dtype", ["int32", "int64"])
+def test_csf_pack_matches_oracle(gpu_lib, crd_dtype):
+    """The pack against the oracle's CSF for every order r = 1..8, with duplicates (separate
+    leaves), sizes spanning several 2048-record tiles with ragged tails and exact multiples."""
     import torch
     from oracle import csf
-    rng = np.random.default_rng(12)
-    for trial in range(6):
-        r = int(rng.integers(1, 5))
+    rng = np.random.default_rng(12 if crd_dtype == "int32" else 13)
+    sizes = [1, 2047, 2048, 2049, 4096, 6145, 20000, 40000]
+    for trial, r in enumerate(list(range(1, 9)) + [int(x) for x in rng.integers(1, 9, size=4)]):
         ext = tuple(int(x) for x in rng.integers(1, 12, size=r))
         sigma = tuple(int(x) for x in rng.permutation(r))
-        n = int(rng.integers(1, 20000))
-        T = make_tensor(ext, n, in_order=sigma, seed=trial, distinct=False)  # already sigma-sorted
-        note(f"csf r={r} n={n} ext={ext} sigma={sigma}")
-        P = gpu_lib.Plan(ext, sigma, sigma, n)
+        n = sizes[trial % len(sizes)]
+        T = make_tensor(ext, n, in_order=sigma, seed=trial, distinct=False,
+                        crd_dtype=np.dtype(crd_dtype))  # already sigma-sorted
+        note(f"csf r={r} n={n} ext={ext} sigma={sigma} {crd_dtype}")
+        P = gpu_lib.Plan(ext, sigma, sigma, n, crd_dtype, "float64")
         crd, _ = dev(T)
         pos, lev, counts = P.pack_csf(crd)
+        torch.cuda.synchronize()
+        assert P.device_status() == 0
         want_pos, want_lev = csf.pack_csf([c.tolist() for c in T.crd], sigma)
-        assert counts[0] == 1 and counts[-1] == n
+        assert counts == [1] + [len(lv) for lv in want_lev]
         for d in range(r):
             assert pos[d].cpu().tolist() == want_pos[d], f"pos level {d + 1}"
             assert lev[d].cpu().tolist() == want_lev[d], f"crd level {d + 1}"
