@@ -12,7 +12,8 @@
 
 namespace qsd {
 
-constexpr int kCsfTile = 2048;  // records per tile of the CSF pack
+// records per tile of the CSF pack (the smallest tile: the look-back words are sized by it)
+constexpr int kCsfTile = 2048;
 
 struct CsfArgs {
     const void* crd[8];         // sorted coordinates in level order: crd[d] is mode sigma_{d+1}

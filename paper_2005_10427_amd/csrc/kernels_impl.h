@@ -166,8 +166,10 @@ __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32
 
 // Counts of every digit of every pass of one key, over all records (global) or per large
 // segment.  Also clears the look-back words of the key's first digit pass.
+// At most 64 registers (eight waves per SIMD): the kernel waits on its loads, and more waves in
+// flight hide them better (plain workload: 227 -> 219 us per launch).
 template <int R, typename CT>
-__global__ void __launch_bounds__(256) k_hist(HistArgs a) {
+__global__ void __launch_bounds__(256, 8) k_hist(HistArgs a) {
     constexpr int U = kHistU;
     constexpr int MAXP = 16;
     __shared__ uint32_t s_h[MAXP * kBins + kBins];  // + one spare block for out-of-range items
