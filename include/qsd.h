@@ -222,6 +222,21 @@ qsd_status qsd_batch_workspace_max(qsd_batch_t batch, size_t* bytes);
 qsd_status qsd_batch_tune(qsd_batch_t batch, const qsd_batch_io* io, void* ws, size_t ws_bytes,
                           hipStream_t stream, int32_t reps, qsd_tuning* best, float* best_ms);
 
+/* Autotune cache.  The key of a batch names the device architecture, the coordinate and value
+ * widths, the largest order and the size class (floor(log2(total nonzeros + 1)) and
+ * floor(log2(tensors))), e.g. "gfx950/c4/v8/r4/n29/t12"; key_bytes >= 64 is enough.
+ * qsd_batch_tune_cached looks the key up in the text file at cache_path (one entry per line:
+ * key items radix_bits small_cap ms); on a hit it applies and binds that tuning without timing
+ * (*from_cache = 1, *best_ms = the recorded time; the first matching line is used), otherwise it
+ * runs qsd_batch_tune and appends the result (*from_cache = 0).  A missing file is a miss, lines
+ * that do not parse are skipped, an entry that qsd_batch_set_tuning rejects or whose workspace
+ * exceeds ws_bytes is tuned afresh, and a file that cannot be written leaves the result uncached
+ * (not an error).  Concurrent writers to one file are not coordinated. */
+qsd_status qsd_batch_tune_key(qsd_batch_t batch, char* key, size_t key_bytes);
+qsd_status qsd_batch_tune_cached(qsd_batch_t batch, const qsd_batch_io* io, void* ws, size_t ws_bytes,
+                                 hipStream_t stream, int32_t reps, const char* cache_path, qsd_tuning* best,
+                                 float* best_ms, int32_t* from_cache);
+
 /* HIP graph of qsd_batch_transpose on the bound workspace: captured on an internal stream and
  * instantiated; launch it on any stream.  The graph holds the buffer addresses bound now. */
 typedef struct qsd_graph_s* qsd_graph_t;

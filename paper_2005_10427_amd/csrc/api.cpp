@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -1380,6 +1381,68 @@ done:
     if (best) *best = bt;
     if (best_ms) *best_ms = bms;
     return st;
+}
+
+qsd_status qsd_batch_tune_key(qsd_batch_t b, char* key, size_t key_bytes) {
+    if (!b || !key) return QSD_ERR_NULL;
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return QSD_ERR_HIP;
+    std::string arch(prop.gcnArchName);
+    arch = arch.substr(0, arch.find(':'));  // without the feature suffixes
+    uint64_t nnz = 0;
+    for (const auto& x : b->t) nnz += x.n;
+    auto lg = [](uint64_t v) { int k = 0; while (v > 1) { v >>= 1; ++k; } return k; };
+    const std::string k = arch + "/c" + std::to_string(b->crd_bytes) + "/v" + std::to_string(b->val_bytes) + "/r" +
+                          std::to_string(b->rmax) + "/n" + std::to_string(lg(nnz + 1)) + "/t" +
+                          std::to_string(lg(std::max<uint64_t>(b->t.size(), 1)));
+    if (k.size() + 1 > key_bytes) return QSD_ERR_TOO_LARGE;
+    std::memcpy(key, k.c_str(), k.size() + 1);
+    return QSD_OK;
+}
+
+qsd_status qsd_batch_tune_cached(qsd_batch_t b, const qsd_batch_io* io, void* ws, size_t ws_bytes,
+                                 hipStream_t stream, int32_t reps, const char* cache_path, qsd_tuning* best,
+                                 float* best_ms, int32_t* from_cache) {
+    if (!b || !ws || !cache_path) return QSD_ERR_NULL;
+    if (from_cache) *from_cache = 0;
+    char key[128];
+    qsd_status st = qsd_batch_tune_key(b, key, sizeof(key));
+    if (st != QSD_OK) return st;
+    if (FILE* f = std::fopen(cache_path, "r")) {
+        char line[256], k[128];
+        qsd_tuning t{};
+        float ms = 0.f;
+        bool hit = false;
+        while (!hit && std::fgets(line, sizeof(line), f))  // the first matching line is used
+            hit = std::sscanf(line, "%127s %d %d %d %f", k, &t.items, &t.radix_bits, &t.small_cap, &ms) == 5 &&
+                  std::strcmp(k, key) == 0;
+        std::fclose(f);
+        if (hit) {
+            const qsd_tuning old = b->tun;
+            if (qsd_batch_set_tuning(b, &t) == QSD_OK && b->total <= ws_bytes) {
+                st = qsd_batch_bind(b, io, ws, ws_bytes, stream);
+                if (st == QSD_OK) {
+                    if (best) *best = t;
+                    if (best_ms) *best_ms = ms;
+                    if (from_cache) *from_cache = 1;
+                }
+                return st;
+            }
+            qsd_batch_set_tuning(b, &old);  // unusable entry: tune afresh
+        }
+    }
+    qsd_tuning t{};
+    float ms = 0.f;
+    st = qsd_batch_tune(b, io, ws, ws_bytes, stream, reps, &t, &ms);
+    if (st != QSD_OK) return st;
+    if (FILE* f = std::fopen(cache_path, "a")) {
+        std::fprintf(f, "%s %d %d %d %.4f\n", key, t.items, t.radix_bits, t.small_cap, ms);
+        std::fclose(f);
+    }
+    if (best) *best = t;
+    if (best_ms) *best_ms = ms;
+    return QSD_OK;
 }
 
 qsd_status qsd_batch_graph(qsd_batch_t b, void* ws, size_t ws_bytes, qsd_graph_t* out) {

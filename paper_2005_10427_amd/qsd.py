@@ -103,6 +103,10 @@ def load():
     lib.qsd_batch_transpose.argtypes = [_VP, _VP, ctypes.c_size_t, _VP]
     lib.qsd_batch_tune.argtypes = [_VP, ctypes.POINTER(qsd_batch_io), _VP, ctypes.c_size_t, _VP, ctypes.c_int32,
                                    ctypes.POINTER(qsd_tuning), ctypes.POINTER(ctypes.c_float)]
+    lib.qsd_batch_tune_key.argtypes = [_VP, ctypes.c_char_p, ctypes.c_size_t]
+    lib.qsd_batch_tune_cached.argtypes = [_VP, ctypes.POINTER(qsd_batch_io), _VP, ctypes.c_size_t, _VP, ctypes.c_int32,
+                                          ctypes.c_char_p, ctypes.POINTER(qsd_tuning), ctypes.POINTER(ctypes.c_float),
+                                          ctypes.POINTER(ctypes.c_int32)]
     lib.qsd_batch_graph.argtypes = [_VP, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]
     lib.qsd_graph_launch.argtypes = [_VP, _VP]
     lib.qsd_graph_destroy.argtypes = [_VP]
@@ -144,7 +148,8 @@ def load():
                  "qsd_csf_transpose_workspace", "qsd_csf_transpose",
                  "qsd_profile_stop", "qsd_batch_plan", "qsd_batch_set_tuning", "qsd_batch_get_tuning",
                  "qsd_batch_workspace", "qsd_batch_workspace_max", "qsd_batch_bind", "qsd_batch_transpose",
-                 "qsd_batch_tune", "qsd_batch_graph", "qsd_graph_launch"):
+                 "qsd_batch_tune", "qsd_batch_tune_key", "qsd_batch_tune_cached", "qsd_batch_graph",
+                 "qsd_graph_launch"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -321,6 +326,23 @@ def qsd_batch_tune(batch, ios, ws, ws_bytes, stream, reps=3):
     _check(load().qsd_batch_tune(batch, _ios(ios), ws, int(ws_bytes), stream, int(reps), ctypes.byref(t),
                                  ctypes.byref(ms)), "qsd_batch_tune")
     return (t.items, t.radix_bits, t.small_cap), ms.value
+
+
+def qsd_batch_tune_key(batch):
+    buf = ctypes.create_string_buffer(128)
+    _check(load().qsd_batch_tune_key(batch, buf, len(buf)), "qsd_batch_tune_key")
+    return buf.value.decode()
+
+
+def qsd_batch_tune_cached(batch, ios, ws, ws_bytes, stream, cache_path, reps=3):
+    """Returns ((items, radix_bits, small_cap), best_ms, from_cache)."""
+    t = qsd_tuning()
+    ms = ctypes.c_float()
+    hit = ctypes.c_int32()
+    _check(load().qsd_batch_tune_cached(batch, _ios(ios), ws, int(ws_bytes), stream, int(reps),
+                                        str(cache_path).encode(), ctypes.byref(t), ctypes.byref(ms),
+                                        ctypes.byref(hit)), "qsd_batch_tune_cached")
+    return (t.items, t.radix_bits, t.small_cap), ms.value, bool(hit.value)
 
 
 def qsd_batch_graph(batch, ws, ws_bytes):
@@ -653,8 +675,17 @@ class Batch:
     def tuning(self):
         return qsd_batch_get_tuning(self.handle)
 
-    def tune(self, reps=3, stream=None):
+    def tune(self, reps=3, stream=None, cache=None):
+        """The autotuner; with `cache` (a file path) a cached tuning for this batch's key is
+        applied without timing, and a new result is appended.  Returns (tuning, ms) without a
+        cache, (tuning, ms, from_cache) with one."""
+        if cache is not None:
+            return qsd_batch_tune_cached(self.handle, self._io(), self.ws.data_ptr(), self.ws_bytes,
+                                         self._stream(stream), cache, reps)
         return qsd_batch_tune(self.handle, self._io(), self.ws.data_ptr(), self.ws_bytes, self._stream(stream), reps)
+
+    def tune_key(self):
+        return qsd_batch_tune_key(self.handle)
 
     def transpose(self, stream=None):
         qsd_batch_transpose(self.handle, self.ws.data_ptr(), self.ws_bytes, self._stream(stream))

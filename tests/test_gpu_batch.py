@@ -100,6 +100,34 @@ def test_batch_autotune_then_transpose(gpu_lib):
     _check_all(T, out_crd, out_val)
 
 
+def test_batch_autotune_cache(gpu_lib, tmp_path):
+    """First call: a miss that tunes and appends one line; a second batch of the same key: a
+    hit that applies the recorded tuning without timing; both transpose correctly.  Lines that
+    do not parse and other keys are skipped."""
+    cache = tmp_path / "tune.txt"
+    cache.write_text("not a cache line\ngfx0/c4/v8/r9/n1/t1 8 6 0 1.0\n")
+    T = _batch(count=16, seed=11)
+    B = gpu_lib.Batch([t.as_dict() for t in T])
+    key = B.tune_key()
+    note(f"key {key}")
+    assert key.split("/")[0].startswith("gfx") and "/c4/v8/" in key
+    best, ms, hit = B.tune(reps=1, cache=cache)
+    assert not hit and ms > 0
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 3 and lines[-1].split()[0] == key
+    assert tuple(int(x) for x in lines[-1].split()[1:4]) == best
+    B2 = gpu_lib.Batch([t.as_dict() for t in T])
+    assert B2.tune_key() == key
+    best2, ms2, hit2 = B2.tune(reps=1, cache=cache)
+    assert hit2 and best2 == best and B2.tuning() == best and ms2 == pytest.approx(float(lines[-1].split()[4]))
+    assert len(cache.read_text().splitlines()) == 3  # a hit appends nothing
+    for c in B2.out_val:
+        c.zero_()
+    out_crd, out_val = B2.transpose()
+    assert B2.device_status() == 0
+    _check_all(T, out_crd, out_val)
+
+
 def test_batch_graph_replays_match_eager(gpu_lib):
     import torch
     T = _batch(count=24, seed=10)
