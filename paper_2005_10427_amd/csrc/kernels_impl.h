@@ -52,12 +52,27 @@ __device__ __forceinline__ void sync_after_lds_atomics() {
 __device__ __forceinline__ uint32_t from_lane_below(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
 }
-// One count per lane into s_h[slot].  Consecutive lanes holding the same slot (long runs in
-// sorted inputs) are added once, from the run's first lane, by the run's length, instead of
-// one conflicting atomic per lane.  When at least half of the lanes start a run (the usual case
-// for unsorted digits, where the few repeated slots cost the LDS little) each lane adds 1
-// directly, skipping the run lengths.  Either way every lane is counted once.
+// Values that are the same in every lane, moved into scalar registers.
+__device__ __forceinline__ uint32_t uni32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    return ((uint64_t)uni32((uint32_t)(v >> 32)) << 32) | uni32((uint32_t)v);
+}
+template <typename P>
+__device__ __forceinline__ P* uni_ptr(P* p) {
+    return reinterpret_cast<P*>(uni64(reinterpret_cast<uint64_t>(p)));
+}
+// One count per lane into s_h[slot].  A wave whose lanes all hold one slot (sorted digits)
+// adds 64 once.  Otherwise consecutive lanes holding the same slot (long runs in sorted
+// inputs) are added once, from the run's first lane, by the run's length, instead of one
+// conflicting atomic per lane; when at least half of the lanes start a run (the usual case for
+// unsorted digits, where the few repeated slots cost the LDS little) each lane adds 1
+// directly, skipping the run lengths.  Every lane is counted once.
 __device__ __forceinline__ void count_slot(uint32_t* s_h, uint32_t slot, int lane) {
+    const uint32_t s0 = uni32(slot);
+    if (ballot(slot != s0) == 0) {  // one slot in the whole wave (sorted digits): one add of 64
+        if (lane == 0) atomicAdd(&s_h[s0], 64u);
+        return;
+    }
     // lane 0 always starts a run: the value "below" it is ~0, which no slot equals
     const uint64_t heads = ballot(from_lane_below(slot) != slot);
     if (__popcll(heads) >= 32) {
@@ -67,15 +82,6 @@ __device__ __forceinline__ void count_slot(uint32_t* s_h, uint32_t slot, int lan
         const uint32_t run = after ? (uint32_t)__builtin_ctzll(after) + 1u : 64u - lane;
         atomicAdd(&s_h[slot], run);
     }
-}
-// Uniform values read from LDS into scalar registers.
-__device__ __forceinline__ uint32_t uni32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
-__device__ __forceinline__ uint64_t uni64(uint64_t v) {
-    return ((uint64_t)uni32((uint32_t)(v >> 32)) << 32) | uni32((uint32_t)v);
-}
-template <typename P>
-__device__ __forceinline__ P* uni_ptr(P* p) {
-    return reinterpret_cast<P*>(uni64(reinterpret_cast<uint64_t>(p)));
 }
 // number of set bits of m in lanes below this one
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
