@@ -1513,9 +1513,11 @@ hipError_t launch_persistent(K kern, int& resident, const DigitArgs& a, hipStrea
 template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK = 0>
 hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
     static int resident = 0;
-    // packed words in (R = 1 with 64-bit words, or unpacking) and the packing pass: three
-    // workgroups per CU
-    if constexpr (MODE != 1 && ITEMS == 16 && (PK == 2 || (R == 1 && sizeof(CT) == 8)))
+    // packed words in (R = 1 with 64-bit words, or unpacking), and the packing pass of records of
+    // at most 20 bytes (at most 12 bytes of spill; the 3-mode int32/fp64 packing pass: 895 ->
+    // 837 us per launch): three workgroups per CU
+    constexpr bool kPack3 = PK == 1 && R * sizeof(CT) + sizeof(VT) <= 20;
+    if constexpr (MODE != 1 && ITEMS == 16 && (PK == 2 || kPack3 || (R == 1 && sizeof(CT) == 8)))
         return launch_persistent(k_digit3<R, CT, VT, ITEMS, MODE, PK>, resident, a, s);
     else
         return launch_persistent(k_digit<R, CT, VT, ITEMS, MODE, PK>, resident, a, s);
