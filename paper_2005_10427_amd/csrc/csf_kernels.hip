@@ -40,10 +40,9 @@ __device__ __forceinline__ CT csf_lane63(CT x) {
 // or leaf that starts at the same record), the leaves in place.
 //
 // Persistent workgroups take tiles of csf_tile<R, CT>() records in increasing order from one
-// counter;
-// all R coordinate arrays of a tile are loaded at once, the previous record of each lane comes
-// from the lane below (DPP) or, for lane 0, from lane 63 of the previous item (the record
-// before a wave's first item is one uniform load).  Per level the tile's starts are counted
+// counter; all R coordinate arrays of a tile are loaded at once, the previous record of each
+// lane comes from the lane below (DPP) or, for lane 0, from lane 63 of the previous item (the
+// record before a wave's first item is one uniform load).  Per level the tile's starts are counted
 // with ballots and numbered by a decoupled look-back over the tiles, one wave per level.
 // Records per tile: as many as the registers allow, since larger tiles mean fewer look-backs
 // and longer runs of contiguous stores: 8192 for r c <= 12 bytes, 4096 for r c <= 16, else
