@@ -258,10 +258,15 @@ hipError_t timed(int kind, double bytes, hipStream_t s, F&& fn) {
     if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return fn();
     std::lock_guard<std::mutex> lk(g_prof_mu);
     ProfRec r{kind, pool_event(), pool_event(), bytes};
-    if (r.a) hipEventRecord(r.a, s);
+    const bool ra = r.a && hipEventRecord(r.a, s) == hipSuccess;
     const hipError_t e = fn();
-    if (r.b) hipEventRecord(r.b, s);
-    g_prof.push_back(r);
+    const bool rb = r.b && hipEventRecord(r.b, s) == hipSuccess;
+    if (ra && rb) {
+        g_prof.push_back(r);
+    } else {  // a launch whose events did not record is left out of the profile
+        if (r.a) (void)hipEventDestroy(r.a);
+        if (r.b) (void)hipEventDestroy(r.b);
+    }
     return e;
 }
 
@@ -770,6 +775,8 @@ qsd_status qsd_pack_csf(qsd_plan_t plan, int64_t nnz, const void* const* sorted_
     return QSD_OK;
 }
 
+}  // extern "C"
+
 // ---- CSF -> CSF: expansion to coordinates, the plan's transposition, the pack
 namespace {
 struct CsfTLayout {
@@ -800,6 +807,8 @@ CsfTLayout csf_t_layout(qsd_plan_t plan) {
     return L;
 }
 }  // namespace
+
+extern "C" {
 
 qsd_status qsd_csf_transpose_workspace(qsd_plan_t plan, size_t* bytes) {
     if (!plan || !bytes) return QSD_ERR_NULL;
@@ -1358,15 +1367,17 @@ qsd_status qsd_batch_tune(qsd_batch_t b, const qsd_batch_io* io, void* ws, size_
                 if ((st = qsd_batch_transpose(b, ws, ws_bytes, stream)) != QSD_OK) goto done;  // warm-up
                 float mn = 1e30f;
                 for (int k = 0; k < reps; ++k) {
-                    hipEventRecord(e0, stream);
-                    if ((st = qsd_batch_transpose(b, ws, ws_bytes, stream)) != QSD_OK) goto done;
-                    hipEventRecord(e1, stream);
-                    if (hipEventSynchronize(e1) != hipSuccess) {
+                    if (hipEventRecord(e0, stream) != hipSuccess) {
                         st = QSD_ERR_HIP;
                         goto done;
                     }
+                    if ((st = qsd_batch_transpose(b, ws, ws_bytes, stream)) != QSD_OK) goto done;
                     float ms = 0.f;
-                    hipEventElapsedTime(&ms, e0, e1);
+                    if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        st = QSD_ERR_HIP;
+                        goto done;
+                    }
                     mn = std::min(mn, ms);
                 }
                 if (bms < 0 || mn < bms) {
@@ -1376,8 +1387,8 @@ qsd_status qsd_batch_tune(qsd_batch_t b, const qsd_batch_io* io, void* ws, size_
             }
     if (qsd_batch_set_tuning(b, &bt) == QSD_OK) st = qsd_batch_bind(b, io, ws, ws_bytes, stream);
 done:
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (best) *best = bt;
     if (best_ms) *best_ms = bms;
     return st;
@@ -1453,19 +1464,19 @@ qsd_status qsd_batch_graph(qsd_batch_t b, void* ws, size_t ws_bytes, qsd_graph_t
     hipGraph_t g = nullptr;
     qsd_status st = QSD_OK;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        hipStreamDestroy(s);
+        (void)hipStreamDestroy(s);
         return QSD_ERR_HIP;
     }
     st = qsd_batch_transpose(b, ws, ws_bytes, s);
     const hipError_t ec = hipStreamEndCapture(s, &g);
-    hipStreamDestroy(s);
+    (void)hipStreamDestroy(s);
     if (st != QSD_OK || ec != hipSuccess || !g) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return st != QSD_OK ? st : QSD_ERR_HIP;
     }
     auto* gr = new qsd_graph_s();
     const hipError_t ei = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (ei != hipSuccess) {
         delete gr;
         return QSD_ERR_HIP;
@@ -1481,7 +1492,7 @@ qsd_status qsd_graph_launch(qsd_graph_t g, hipStream_t stream) {
 
 void qsd_graph_destroy(qsd_graph_t g) {
     if (!g) return;
-    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
     delete g;
 }
 

@@ -31,7 +31,7 @@ qsd_status scratch_on(int dev, void** out) {
         if (cur != dev && hipSetDevice(dev) != hipSuccess) return QSD_ERR_HIP;
         void* p = nullptr;
         const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
-        if (cur != dev) hipSetDevice(cur);
+        if (cur != dev && hipSetDevice(cur) != hipSuccess) return QSD_ERR_HIP;
         if (e != hipSuccess || !p) return QSD_ERR_HIP;
         g_scratch[dev] = p;
     }

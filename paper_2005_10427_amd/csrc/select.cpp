@@ -407,7 +407,7 @@ qsd_status qsd_model_create(const float* params_host, float margin, int64_t min_
         return QSD_ERR_HIP;
     }
     if (hipMemcpy(m->params, params_host, kNParam * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(m->params);
+        (void)hipFree(m->params);
         delete m;
         return QSD_ERR_HIP;
     }
@@ -435,7 +435,7 @@ qsd_status qsd_model_load(const char* path, qsd_model_t* out) {
 
 void qsd_model_destroy(qsd_model_t m) {
     if (!m) return;
-    if (m->params) hipFree(m->params);
+    if (m->params) (void)hipFree(m->params);
     delete m;
 }
 
