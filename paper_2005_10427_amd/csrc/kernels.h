@@ -97,7 +97,7 @@ struct DigitArgs {
     const uint32_t* hist;       // this pass's digit histogram (segment mode: of segment 0)
     uint32_t* status;           // look-back words of this pass, kBins per tile
     uint32_t* status_next;      // zeroed for the next pass (may be null)
-    uint32_t* tile_counter;     // global and batch modes: kPassCounters queues; segment mode: one
+    uint32_t* tile_counter;     // kPassCounters tile queues (one queue below 2048 tiles)
     const uint64_t* large_ctl;  // segment mode
     const SegRec* large;        // segment mode
     const uint32_t* tile_map;   // segment mode: large segment of every tile; batch mode: four

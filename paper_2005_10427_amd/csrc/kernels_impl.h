@@ -495,12 +495,12 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
 
     for (;;) {
         if (tid < 64) {
-            // global and batch modes: queue q (of G) hands out chunks q, q + G, q + 2G, ... of
-            // kTileChunk consecutive (launch) tiles.  Every queue has a workgroup (G <= grid),
+            // queue q (of G) hands out chunks q, q + G, q + 2G, ... of kTileChunk consecutive
+            // (launch) tiles.  Every queue has a workgroup (G <= grid),
             // each queue's tiles go out in increasing order, and a tile waits only for lower
             // tiles, so the lowest unfinished tile always has a running workgroup or a free one
             // that will take it.  Wave 0 computes the geometry (lane 0 takes the tile).
-            const uint32_t G = (MODE != 1 && a.ntiles >= kQueueMinTiles) ? min(kTileQueues, gridDim.x) : 1u;
+            const uint32_t G = a.ntiles >= kQueueMinTiles ? min(kTileQueues, gridDim.x) : 1u;
             const uint32_t qi = blockIdx.x % G;
             uint32_t taken = 0;
             if (tid == 0) taken = atomicAdd(a.tile_counter + qi, 1u);
@@ -508,13 +508,14 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
             uint32_t t = lt, ntiles = a.ntiles, start = 0, len = 0, base = 0, k = 0, lowest = 0;
             bool live = false;
             if (MODE == 1) {
-                ntiles = (uint32_t)*a.large_ctl;
-                if (lt < ntiles) {
-                    k = a.tile_map[lt];
+                ntiles = (uint32_t)*a.large_ctl;  // a.ntiles: the host's upper bound
+                t = ((lt / kTileChunk) * G + qi) * kTileChunk + lt % kTileChunk;
+                if (t < ntiles) {
+                    k = a.tile_map[t];
                     const SegRec s = a.large[k];
                     base = s.start;
                     lowest = s.tile_base;
-                    start = s.start + (lt - s.tile_base) * TILE;
+                    start = s.start + (t - s.tile_base) * TILE;
                     len = min((uint32_t)TILE, s.start + s.len - start);
                     live = true;
                 }
@@ -1513,11 +1514,11 @@ hipError_t launch_persistent(K kern, int& resident, const DigitArgs& a, hipStrea
 template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK = 0>
 hipError_t digit_rs(const DigitArgs& a, hipStream_t s) {
     static int resident = 0;
-    // packed words in (R = 1 with 64-bit words, or unpacking), and the packing pass of records of
-    // at most 20 bytes (at most 12 bytes of spill; the 3-mode int32/fp64 packing pass: 895 ->
-    // 837 us per launch): three workgroups per CU
-    constexpr bool kPack3 = PK == 1 && R * sizeof(CT) + sizeof(VT) <= 20;
-    if constexpr (MODE != 1 && ITEMS == 16 && (PK == 2 || kPack3 || (R == 1 && sizeof(CT) == 8)))
+    // packed words in (R = 1 with 64-bit words, or unpacking), and records of at most 20 bytes
+    // in (at most 12 bytes of spill; the 3-mode int32/fp64 packing pass: 895 -> 837 us per
+    // launch): three workgroups per CU
+    constexpr bool kSmallRec = R * sizeof(CT) + sizeof(VT) <= 20;
+    if constexpr (ITEMS == 16 && (PK == 2 || kSmallRec || (R == 1 && sizeof(CT) == 8)))
         return launch_persistent(k_digit3<R, CT, VT, ITEMS, MODE, PK>, resident, a, s);
     else
         return launch_persistent(k_digit<R, CT, VT, ITEMS, MODE, PK>, resident, a, s);
