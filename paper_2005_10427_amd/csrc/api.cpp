@@ -31,7 +31,7 @@ struct Layout {
     size_t hist_words = 0;
     size_t status[2] = {};
     size_t status_words = 0;  // per array
-    size_t seg_start = 0, region_seg = 0, bstatus = 0, bstatus_words = 0, med = 0, large = 0, seg_hist = 0;
+    size_t seg_start = 0, region_seg = 0, bstatus = 0, bstatus_words = 0, geo = 0, large = 0, seg_hist = 0;
     size_t tile_map = 0;
     size_t pk[2] = {};        // packed-record ping-pong buffers (64-bit words)
     size_t seg_bits = 0;      // segment starts as one bit per record (bucket reuse)
@@ -148,8 +148,8 @@ void make_layout(qsd_plan_s* q) {
         L.bstatus_words = cdiv(N, kBoundTile);
         L.bstatus = at;
         at = up(at + L.bstatus_words * 4 * q->nseg_groups);
-        L.med = at;
-        at = up(at + (size_t)L.max_med * 8);
+        L.geo = at;
+        at = up(at + (cdiv(N, kRegion) + L.max_med) * 16);
         L.large = at;
         at = up(at + (size_t)L.max_large * sizeof(SegRec));
         L.seg_hist = at;
@@ -344,7 +344,7 @@ qsd_status qsd_plan_describe(qsd_plan_t plan, char* buf, size_t len) {
     s += "layout tile=" + std::to_string(plan->tile) + " ctl=" + std::to_string(L.ctl) +
          " status0=" + std::to_string(L.status[0]) + " status1=" + std::to_string(L.status[1]) +
          " seg_start=" + std::to_string(L.seg_start) + " region_seg=" + std::to_string(L.region_seg) +
-         " tile_map=" + std::to_string(L.tile_map) + " med=" + std::to_string(L.med) +
+         " tile_map=" + std::to_string(L.tile_map) + " geo=" + std::to_string(L.geo) +
          " large=" + std::to_string(L.large) + " seg_hist=" + std::to_string(L.seg_hist) +
          " seg_bits=" + std::to_string(L.seg_bits) + " reuse=" + std::to_string(std::count(plan->reuse.begin(), plan->reuse.end(), 1)) +
          " total=" + std::to_string(L.total) + "\n";
@@ -531,7 +531,7 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
         uint32_t* region_seg = (uint32_t*)(W + L.region_seg);
         uint32_t* tile_map = (uint32_t*)(W + L.tile_map);
         uint32_t* bstatus = (uint32_t*)(W + L.bstatus) + (size_t)gseg * L.bstatus_words;
-        uint2* med = (uint2*)(W + L.med);
+        uint4* geo = (uint4*)(W + L.geo);
         SegRec* large = (SegRec*)(W + L.large);
         uint32_t* seg_hist = (uint32_t*)(W + L.seg_hist);
         uint64_t* large_ctl = (uint64_t*)(ctl + kCtlLarge);
@@ -576,7 +576,9 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
         ca.nb = ctl + kCtlNb;
         ca.tile = T;
         ca.nmed = ctl + kCtlNMed;
-        ca.med = med;
+        ca.geo = geo;
+        ca.region_seg = region_seg;
+        ca.nregions = (n + kRegion - 1) / kRegion;
         ca.large_ctl = large_ctl;
         ca.large = large;
         ca.tile_map = tile_map;
@@ -597,9 +599,8 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
         sa.n = n;
         sa.nregions = (n + kRegion - 1) / kRegion;
         sa.seg_start = seg_start;
-        sa.region_seg = region_seg;
         sa.nmed = ctl + kCtlNMed;
-        sa.med = med;
+        sa.geo = geo;
         const uint32_t small_items = sa.nregions + (uint32_t)std::min<uint64_t>(L.max_med, n / (kTinyLen + 1) + 1);
         QSD_CK(timed(kSmall, 0, stream, [&] { return launch_small(sa, p.crd_bytes, p.val_bytes, small_items, stream); }));
 

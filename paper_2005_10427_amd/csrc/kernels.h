@@ -193,7 +193,10 @@ struct ClassArgs {
     const uint32_t* nb;
     uint32_t tile;              // digit-pass tile of the large path
     uint32_t* nmed;
-    uint2* med;
+    uint4* geo;                 // per work item of the LDS sort: first record, records, first and
+                                // end segment (regions first, then the medium segments)
+    const uint32_t* region_seg;
+    uint32_t nregions;
     uint64_t* large_ctl;
     SegRec* large;
     uint32_t* tile_map;
@@ -212,9 +215,8 @@ struct SmallArgs {
     uint32_t n;
     uint32_t nregions;
     const uint32_t* seg_start;
-    const uint32_t* region_seg;
     const uint32_t* nmed;
-    const uint2* med;
+    const uint4* geo;           // work items as written by k_classify
 };
 
 struct ZeroArgs {

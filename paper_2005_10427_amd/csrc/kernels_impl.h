@@ -888,17 +888,28 @@ __global__ void __launch_bounds__(256) k_boundary(BoundArgs a) {
     }
 }
 
-// Sort segments into three classes: tiny (left to the region pass), medium (one workgroup
-// each) and large (digit passes over tiles of the segment).
+// Sort segments into three classes: tiny (sorted together with the other tiny segments that
+// start in the same region), medium (one workgroup each) and large (digit passes over tiles of
+// the segment).  Writes the LDS sort's work items: one per region, then one per medium segment.
 __global__ void __launch_bounds__(256) k_classify(ClassArgs a) {
     const uint32_t nb = *a.nb;
-    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nb; k += gridDim.x * kBlock) {
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < a.nregions; r += stride) {
+        // segments starting in [r*kRegion, (r+1)*kRegion): sa .. se-1; only the last of them
+        // can be longer than the region (kTinyLen == kRegion), and it is left out if it is
+        const uint32_t sa = a.region_seg[r];
+        uint32_t se = a.region_seg[r + 1];
+        if (se > sa && a.seg_start[se] - a.seg_start[se - 1] > (uint32_t)kTinyLen) --se;
+        const uint32_t rs = a.seg_start[sa];
+        a.geo[r] = make_uint4(rs, a.seg_start[se] - rs, sa, se);
+    }
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nb; k += stride) {
         const uint32_t s = a.seg_start[k];
         const uint32_t len = a.seg_start[k + 1] - s;
         if (len <= (uint32_t)kTinyLen) continue;
         if (len <= (uint32_t)kSmallCap) {
             const uint32_t i = atomicAdd(a.nmed, 1u);
-            a.med[i] = make_uint2(s, len);
+            a.geo[a.nregions + i] = make_uint4(s, len, 0, 0);
         } else {
             const uint32_t tiles = (len + a.tile - 1) / a.tile;
             const unsigned long long old =
@@ -917,16 +928,52 @@ __global__ void __launch_bounds__(256) k_classify(ClassArgs a) {
     }
 }
 
-// Stable sort of short runs of records entirely in LDS, by (segment number, group key).
-// Work items: the tiny segments starting in each region of kRegion records (their union
-// is one run of fewer than kSmallCap records), then every medium segment.  A run's records
-// are loaded into registers right away (all loads in flight at once), sorted through LDS
-// by LSD passes over the key bits that vary inside the run, and written back in place.
+// Range-checked access to the n elements of type T from base through a buffer resource: a
+// load outside returns 0 and a store outside is dropped, neither touching memory, and neither
+// needs a branch (a branch per element would wait for each load before the next).  The scalar
+// offset, which the hardware range check does not cover on gfx9-family targets, is always 0.
+using u32x2 = uint32_t __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t elem_rsrc(const void* base, uint32_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)(n * sizeof(T)), kBufferWord3);
+}
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, int off) {
+    if constexpr (sizeof(T) == 8) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        return (T)(((uint64_t)w[1] << 32) | w[0]);
+    } else {
+        return (T)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void buf_st(T v, __amdgpu_buffer_rsrc_t r, int off) {
+    if constexpr (sizeof(T) == 8) {
+        u32x2 w;
+        w[0] = (uint32_t)(uint64_t)v;
+        w[1] = (uint32_t)((uint64_t)v >> 32);
+        __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)v, r, off, 0, 0);
+    }
+}
+
+// Stable sort of short runs of records in LDS, by (segment number, group key).  Work items
+// (k_classify): the tiny segments starting in each region of kRegion records (their union is
+// one run of fewer than kSmallCap records), then every medium segment.  Only the key modes are
+// loaded up front; each thread keeps the 64-bit keys of its slots in registers, and every LSD
+// pass over the key bits that vary inside the run publishes one digit byte per slot and moves
+// 16-bit slot numbers through LDS.  The records are then gathered in sorted order straight from
+// global memory (the key modes were just read: mostly cache hits) and written back at the same
+// positions of the destination, which may be the source itself.  With no records held in
+// registers and 26 KB of LDS, several runs share a CU; the next item's geometry is loaded one
+// item ahead.
 template <int R, typename CT, typename VT>
-__global__ void __launch_bounds__(256) k_small(SmallArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_small(SmallArgs a) {
     constexpr int CAP = kSmallCap, ITEMS = CAP / kBlock;
-    __shared__ uint64_t s_key[CAP];   // keys, then staging of each array
-    __shared__ uint16_t s_ia[CAP], s_ib[CAP], s_seg[CAP];
+    static_assert(kTinyLen == kRegion && kRegion + kTinyLen <= kSmallCap, "a region run must fit");
+    __shared__ uint16_t s_ia[CAP], s_ib[CAP];  // slot permutations; s_ib first holds segment numbers
+    __shared__ uint8_t s_dig[CAP];             // this pass's digit of every slot
     __shared__ uint32_t s_cnt[kWaves * kBins];
     __shared__ uint32_t s_bstart[kBins];
     __shared__ uint32_t s_tmp[2 * kWaves];
@@ -934,90 +981,92 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
     __shared__ uint32_t s_run[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    for (uint32_t item = blockIdx.x;; item += gridDim.x) {
-        const uint32_t nmed = *a.nmed;
-        if (item >= a.nregions + nmed) break;
+    // written by the previous kernel: fixed for the whole launch
+    const uint32_t nitems = a.nregions + *a.nmed;
+    uint4 gnext = make_uint4(0, 0, 0, 0);  // thread 0: geometry of the workgroup's next item
+    if (tid == 0 && blockIdx.x < nitems) gnext = a.geo[blockIdx.x];
+    for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         if (tid == 0) {
-            uint32_t rs = 0, re = 0, sa = 0, se = 0;
-            if (item < a.nregions) {
-                // segments starting in [item*kRegion, (item+1)*kRegion): sa .. se-1
-                sa = a.region_seg[item];
-                se = a.region_seg[item + 1];
-                // only the last segment starting here can be longer than the region
-                if (se > sa && a.seg_start[se] - a.seg_start[se - 1] > (uint32_t)kTinyLen) --se;
-                rs = a.seg_start[sa];
-                re = a.seg_start[se];
-            } else {
-                const uint2 md = a.med[item - a.nregions];
-                rs = md.x;
-                re = md.x + md.y;
-            }
-            s_run[0] = rs;
-            s_run[1] = re;
-            s_run[2] = sa;
-            s_run[3] = se;
+            s_run[0] = gnext.x;
+            s_run[1] = gnext.y;
+            s_run[2] = gnext.z;
+            s_run[3] = gnext.w;
+            if (item + gridDim.x < nitems) gnext = a.geo[item + gridDim.x];
         }
         __syncthreads();
+        // the thread's index, opaque per item: slot indices derived from it are recomputed
+        // where they are used instead of being hoisted out of the loop and spilled
+        int ot = tid;
+        asm volatile("" : "+v"(ot));
         const uint32_t rs = __builtin_amdgcn_readfirstlane(s_run[0]);
-        const uint32_t L = __builtin_amdgcn_readfirstlane(s_run[1]) - rs;
+        const uint32_t L = __builtin_amdgcn_readfirstlane(s_run[1]);
         const uint32_t sa = __builtin_amdgcn_readfirstlane(s_run[2]);
         const uint32_t se = __builtin_amdgcn_readfirstlane(s_run[3]);
         if (L == 0) {
             __syncthreads();
             continue;
         }
-        const bool region = item < a.nregions;
 
-        // ---- the whole run into registers: slot j = i*kBlock + tid
-        CT c[R][ITEMS];
-        VT v[ITEMS];
+        // ---- group key of every slot j = i*kBlock + tid (the key modes of a group of modes are
+        // loaded together), and the starts of the run's segments after its first (regions only:
+        // a medium item has sa == se == 0)
+        uint64_t key[ITEMS];
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const CT* src = (const CT*)a.src_crd[m] + rs;
+        for (int i = 0; i < ITEMS; ++i) key[i] = 0;
+        constexpr int KG = sizeof(CT) == 4 ? 4 : 2;  // modes loaded at once
+        uint32_t st[ITEMS / 2];  // at most kRegion segments start in a region
 #pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const uint32_t j = i * kBlock + tid;
-                c[m][i] = j < L ? src[j] : CT(0);
+        for (int m0 = 0; m0 < R; m0 += KG) {
+            CT x[KG][ITEMS];
+#pragma unroll
+            for (int g = 0; g < KG; ++g) {
+                if (m0 + g < R) {
+                    // a mode outside the key gets an empty range: its loads touch no memory
+                    const __amdgpu_buffer_rsrc_t rc =
+                        elem_rsrc<CT>((const CT*)a.src_crd[m0 + g] + rs, a.key.mask[m0 + g] ? L : 0u);
+#pragma unroll
+                    for (int i = 0; i < ITEMS; ++i) x[g][i] = buf_ld<CT>(rc, (int)((i * kBlock + ot) * sizeof(CT)));
+                }
+            }
+            if (m0 == 0) {
+                // seg_start[sa+1 .. se-1]; 0 past the end (never above rs)
+                const __amdgpu_buffer_rsrc_t rc = elem_rsrc<uint32_t>(a.seg_start + sa + 1, se > sa ? se - sa - 1 : 0u);
+#pragma unroll
+                for (int i = 0; i < ITEMS / 2; ++i) st[i] = buf_ld<uint32_t>(rc, (int)((i * kBlock + ot) * 4));
+            }
+#pragma unroll
+            for (int g = 0; g < KG; ++g) {
+                if (m0 + g < R) {
+                    const uint64_t mk = a.key.mask[m0 + g];
+                    const int lo = a.key.src_lo[m0 + g], dst = a.key.dst[m0 + g];
+#pragma unroll
+                    for (int i = 0; i < ITEMS; ++i) key[i] |= (((uint64_t)x[g][i] >> lo) & mk) << dst;
+                }
             }
         }
-        {
-            const VT* src = (const VT*)a.src_val + rs;
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const uint32_t j = i * kBlock + tid;
-                v[i] = j < L ? src[j] : VT(0);
-            }
-        }
 
-        // ---- segment number of every record of the run
+        // ---- segment number of every slot (in s_ib)
+        uint16_t* s_seg = s_ib;
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) s_seg[i * kBlock + tid] = 0;
+        for (int i = 0; i < ITEMS; ++i) s_seg[i * kBlock + ot] = 0;
         __syncthreads();
-        if (region) {
-            uint32_t st[ITEMS / 2];
 #pragma unroll
-            for (int i = 0; i < ITEMS / 2; ++i) {  // at most kRegion segments start in a region
-                const uint32_t s2 = sa + 1 + i * kBlock + tid;
-                st[i] = s2 < se ? a.seg_start[s2] : 0xFFFFFFFFu;
-            }
-#pragma unroll
-            for (int i = 0; i < ITEMS / 2; ++i)
-                if (st[i] != 0xFFFFFFFFu) s_seg[st[i] - rs] = 1;
-        }
+        for (int i = 0; i < ITEMS / 2; ++i)
+            if (st[i] > rs) s_seg[st[i] - rs] = 1;
         __syncthreads();
         {
             // blocked inclusive scan: thread tid owns slots [tid*ITEMS, tid*ITEMS+ITEMS)
             uint32_t loc[ITEMS], sum = 0;
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
-                const uint32_t j = tid * ITEMS + i;
+                const uint32_t j = ot * ITEMS + i;
                 sum += (j < L) ? s_seg[j] : 0;
                 loc[i] = sum;
             }
             const uint32_t before = block_excl_scan(sum, s_tmp, nullptr);
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
-                const uint32_t j = tid * ITEMS + i;
+                const uint32_t j = ot * ITEMS + i;
                 if (j < L) s_seg[j] = (uint16_t)(before + loc[i]);
             }
         }
@@ -1026,16 +1075,11 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
         uint64_t kor = 0, kand = ~0ull;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t j = i * kBlock + tid;
+            const uint32_t j = i * kBlock + ot;
             if (j < L) {
-                uint64_t key = 0;
-#pragma unroll
-                for (int m = 0; m < R; ++m)
-                    if (a.key.mask[m]) key |= (((uint64_t)c[m][i] >> a.key.src_lo[m]) & a.key.mask[m]) << a.key.dst[m];
-                key |= (uint64_t)s_seg[j] << a.key_bits;
-                s_key[j] = key;
-                kor |= key;
-                kand &= key;
+                key[i] |= (uint64_t)s_seg[j] << a.key_bits;
+                kor |= key[i];
+                kand &= key[i];
             }
             s_ia[j] = (uint16_t)j;
         }
@@ -1047,7 +1091,7 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
             s_red[wave] = kor;
             s_red[kWaves + wave] = kand;
         }
-        __syncthreads();
+        __syncthreads();  // also: every read of s_seg is done before s_ib serves as a permutation
         kor = 0;
         kand = ~0ull;
 #pragma unroll
@@ -1056,45 +1100,67 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
             kand &= s_red[kWaves + w];
         }
         const uint64_t vary = kor ^ kand;
-        // ---- LSD passes over the bits that vary inside this run
+        // ---- LSD passes over the bits that vary inside this run.  Each wave ranks one
+        // contiguous quarter of the run (C positions, a multiple of 64), so a short run costs
+        // every wave the same few steps.
         uint16_t* cur = s_ia;
         uint16_t* nxt = s_ib;
+        const uint32_t C = (L + kBlock - 1) / kBlock * 64u;
+        const uint32_t wb = (uint32_t)wave * C + lane;
         if (vary) {
             const int lo = __builtin_ctzll(vary), hi = 63 - __builtin_clzll(vary);
             for (int sh = lo; sh <= hi; sh += 8) {
                 const int nbits = min(8, hi - sh + 1);
                 const uint32_t dmask = (1u << nbits) - 1u;
                 if (((vary >> sh) & dmask) == 0) continue;  // digit constant over the run
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t j = i * kBlock + ot;
+                    if (j < L) s_dig[j] = (uint8_t)((key[i] >> sh) & dmask);
+                }
                 for (int b = lane; b < kBins; b += 64) s_cnt[wave * kBins + b] = 0;
+                __syncthreads();
                 uint32_t dg[ITEMS], lp[ITEMS];
                 uint16_t sv[ITEMS];
-                const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
 #pragma unroll
                 for (int i = 0; i < ITEMS; ++i) {
                     const uint32_t j = wb + i * 64;
-                    const bool ok = j < L;
+                    const bool ok = i * 64u < C && j < L;
                     sv[i] = ok ? cur[j] : 0;
-                    dg[i] = ok ? (uint32_t)(s_key[sv[i]] >> sh) & dmask : 0;
+                    dg[i] = ok ? s_dig[sv[i]] : 0;
+                    lp[i] = 0;
                 }
 #pragma unroll
                 for (int i = 0; i < ITEMS; ++i) {
-                    const bool ok = (wb + i * 64) < L;
-                    const uint32_t d = dg[i];
-                    uint64_t peers = ballot(ok);
-                    for (int b = 0; b < nbits; ++b) {
-                        const bool bit = (d >> b) & 1u;
-                        const uint64_t bb = ballot(bit);
-                        peers &= bit ? bb : ~bb;
+                    if (i * 64u < C) {
+                        const bool ok = (wb + i * 64) < L;
+                        const uint32_t d = dg[i];
+                        // peers: the lanes whose digit equals this lane's.  sm is this lane's bit b
+                        // smeared over the word; lane j agrees with it on bit b iff bit j of
+                        // ~(ballot ^ sm) is set (bitop3 truth table 0x90: acc & ~(x ^ y)).
+                        const uint64_t pk0 = ballot(ok);
+                        uint32_t plo = (uint32_t)pk0, phi = (uint32_t)(pk0 >> 32);
+#pragma unroll
+                        for (int b = 0; b < 8; ++b) {
+                            if (b < nbits) {
+                                uint32_t sm = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+                                asm("" : "+v"(sm));  // opaque: the ballot then compares sm itself
+                                const uint64_t bb = ballot(sm != 0u);
+                                plo = __builtin_amdgcn_bitop3_b32(plo, (uint32_t)bb, sm, 0x90);
+                                phi = __builtin_amdgcn_bitop3_b32(phi, (uint32_t)(bb >> 32), sm, 0x90);
+                            }
+                        }
+                        const uint64_t peers = ((uint64_t)phi << 32) | plo;
+                        const uint32_t below = lanes_below(peers);
+                        uint32_t old = 0;
+                        if (ok) old = s_cnt[wave * kBins + d];
+                        lp[i] = old + below;
+                        if (ok && below == 0) s_cnt[wave * kBins + d] = old + (uint32_t)__popcll(peers);
                     }
-                    const uint32_t below = lanes_below(peers);
-                    uint32_t old = 0;
-                    if (ok) old = s_cnt[wave * kBins + d];
-                    lp[i] = old + below;
-                    if (ok && below == 0) s_cnt[wave * kBins + d] = old + (uint32_t)__popcll(peers);
                 }
                 __syncthreads();
                 {
-                    const uint32_t b = tid;
+                    const uint32_t b = ot;
                     uint32_t run = 0;
 #pragma unroll
                     for (int w = 0; w < kWaves; ++w) {
@@ -1107,7 +1173,7 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
                 __syncthreads();
 #pragma unroll
                 for (int i = 0; i < ITEMS; ++i) {
-                    if ((wb + i * 64) < L) {
+                    if (i * 64u < C && (wb + i * 64) < L) {
                         const uint32_t d = dg[i];
                         nxt[lp[i] + s_bstart[d] + s_cnt[wave * kBins + d]] = sv[i];
                     }
@@ -1118,36 +1184,55 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs a) {
                 nxt = t;
             }
         }
-        // ---- write every array back in sorted order: stage by original slot, gather by perm
-        uint16_t pm[ITEMS];
+        // ---- gather every array in sorted order and write it back at the run's positions.
+        // The destination may be the source: each round's loads have all returned, in every
+        // wave, before any of its stores.
+        uint32_t pm[ITEMS];
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) pm[i] = cur[i * kBlock + tid];
+        for (int i = 0; i < ITEMS; ++i) pm[i] = cur[i * kBlock + ot];
+        auto gather_rounds = [&](auto tag, const void* const* srcs, void* const* dsts, int nar) __attribute__((always_inline)) {
+            using T = decltype(tag);
+            constexpr int G = sizeof(T) == 4 ? 5 : 2;  // arrays per round: at most 80 data VGPRs
 #pragma unroll
-        for (int m = 0; m <= R; ++m) {
-            __syncthreads();
-            if (m < R) {
-                CT* st = (CT*)s_key;
+            for (int m0 = 0; m0 < nar; m0 += G) {
+                T x[G][ITEMS];
 #pragma unroll
-                for (int i = 0; i < ITEMS; ++i) st[i * kBlock + tid] = c[m][i];
-                __syncthreads();
-                CT* dst = (CT*)a.dst_crd[m] + rs;
+                for (int g = 0; g < G; ++g) {
+                    if (m0 + g < nar) {
+                        const __amdgpu_buffer_rsrc_t rc = elem_rsrc<T>((const T*)srcs[m0 + g] + rs, L);
 #pragma unroll
-                for (int i = 0; i < ITEMS; ++i) {
-                    const uint32_t j = i * kBlock + tid;
-                    if (j < L) dst[j] = st[pm[i]];
+                        for (int i = 0; i < ITEMS; ++i) x[g][i] = buf_ld<T>(rc, (int)(pm[i] * sizeof(T)));
+                    }
                 }
-            } else {
-                VT* st = (VT*)s_key;
-#pragma unroll
-                for (int i = 0; i < ITEMS; ++i) st[i * kBlock + tid] = v[i];
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
                 __syncthreads();
-                VT* dst = (VT*)a.dst_val + rs;
 #pragma unroll
-                for (int i = 0; i < ITEMS; ++i) {
-                    const uint32_t j = i * kBlock + tid;
-                    if (j < L) dst[j] = st[pm[i]];
+                for (int g = 0; g < G; ++g) {
+                    if (m0 + g < nar) {
+                        // slots at or past L fall outside the range and are not written
+                        const __amdgpu_buffer_rsrc_t rc = elem_rsrc<T>((T*)dsts[m0 + g] + rs, L);
+#pragma unroll
+                        for (int i = 0; i < ITEMS; ++i) buf_st<T>(x[g][i], rc, (int)((i * kBlock + ot) * sizeof(T)));
+                    }
                 }
             }
+        };
+        if constexpr (sizeof(CT) == sizeof(VT)) {
+            const void* srcs[R + 1];
+            void* dsts[R + 1];
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                srcs[m] = a.src_crd[m];
+                dsts[m] = a.dst_crd[m];
+            }
+            srcs[R] = a.src_val;
+            dsts[R] = a.dst_val;
+            gather_rounds(CT(0), srcs, dsts, R + 1);
+        } else {
+            gather_rounds(CT(0), a.src_crd, a.dst_crd, R);
+            const void* vs[1] = {a.src_val};
+            void* vd[1] = {a.dst_val};
+            gather_rounds(VT(0), vs, vd, 1);
         }
         __syncthreads();
     }
