@@ -31,7 +31,7 @@ struct Layout {
     size_t hist_words = 0;
     size_t status[2] = {};
     size_t status_words = 0;  // per array
-    size_t seg_start = 0, region_seg = 0, bstatus = 0, bstatus_words = 0, geo = 0, large = 0, seg_hist = 0;
+    size_t seg_start = 0, region_seg = 0, bstatus = 0, bstatus_words = 0, geo = 0, seg_hist = 0;
     size_t tile_map = 0;
     size_t pk[2] = {};        // packed-record ping-pong buffers (64-bit words)
     size_t seg_bits = 0;      // segment starts as one bit per record (bucket reuse)
@@ -144,14 +144,12 @@ void make_layout(qsd_plan_s* q) {
         L.region_seg = at;
         at = up(at + (cdiv(N, kRegion) + 2) * 4);
         L.tile_map = at;
-        at = up(at + (size_t)L.max_tiles_large * 4);
+        at = up(at + (size_t)L.max_tiles_large * 16);
         L.bstatus_words = cdiv(N, kBoundTile);
         L.bstatus = at;
         at = up(at + L.bstatus_words * 4 * q->nseg_groups);
         L.geo = at;
         at = up(at + (cdiv(N, kRegion) + L.max_med) * 16);
-        L.large = at;
-        at = up(at + (size_t)L.max_large * sizeof(SegRec));
         L.seg_hist = at;
         at = up(at + (size_t)L.max_large * max_seg_passes * kBins * 4);
     }
@@ -345,7 +343,7 @@ qsd_status qsd_plan_describe(qsd_plan_t plan, char* buf, size_t len) {
          " status0=" + std::to_string(L.status[0]) + " status1=" + std::to_string(L.status[1]) +
          " seg_start=" + std::to_string(L.seg_start) + " region_seg=" + std::to_string(L.region_seg) +
          " tile_map=" + std::to_string(L.tile_map) + " geo=" + std::to_string(L.geo) +
-         " large=" + std::to_string(L.large) + " seg_hist=" + std::to_string(L.seg_hist) +
+         " seg_hist=" + std::to_string(L.seg_hist) +
          " seg_bits=" + std::to_string(L.seg_bits) + " reuse=" + std::to_string(std::count(plan->reuse.begin(), plan->reuse.end(), 1)) +
          " total=" + std::to_string(L.total) + "\n";
     if (len == 0) return QSD_OK;
@@ -529,10 +527,9 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
         const Bufs gdst = hop_dst(h + np - 1);
         uint32_t* seg_start = (uint32_t*)(W + L.seg_start);
         uint32_t* region_seg = (uint32_t*)(W + L.region_seg);
-        uint32_t* tile_map = (uint32_t*)(W + L.tile_map);
+        uint4* tile_geo = (uint4*)(W + L.tile_map);
         uint32_t* bstatus = (uint32_t*)(W + L.bstatus) + (size_t)gseg * L.bstatus_words;
         uint4* geo = (uint4*)(W + L.geo);
-        SegRec* large = (SegRec*)(W + L.large);
         uint32_t* seg_hist = (uint32_t*)(W + L.seg_hist);
         uint64_t* large_ctl = (uint64_t*)(ctl + kCtlLarge);
         if (gseg > 0) {  // counters of the previous segmented group
@@ -580,8 +577,7 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
         ca.region_seg = region_seg;
         ca.nregions = (n + kRegion - 1) / kRegion;
         ca.large_ctl = large_ctl;
-        ca.large = large;
-        ca.tile_map = tile_map;
+        ca.tile_geo = tile_geo;
         ca.seg_hist = seg_hist;
         ca.hist_stride = (uint32_t)np * kBins;
         QSD_CK(timed(kClassify, 0, stream, [&] { return launch_classify(ca, n, stream); }));
@@ -619,10 +615,13 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
         ha.hist_stride = (uint32_t)np * kBins;
         ha.status_zero = S[q % 2];
         ha.large_ctl = large_ctl;
-        ha.large = large;
-        ha.tile_map = tile_map;
+        ha.tile_geo = tile_geo;
         QSD_CK(timed(kHistSeg, 0, stream, [&] {
             return launch_hist(ha, p.r, p.crd_bytes, device_cu_count() * hist_blocks_per_cu(), stream);
+        }));
+        // every pass's digit offsets per large segment, read directly by the segment passes
+        QSD_CK(timed(kHistSeg, 0, stream, [&] {
+            return launch_hist_prefix_seg(seg_hist, large_ctl, (uint32_t)np, L.max_large * (uint32_t)np, stream);
         }));
         const uint32_t max_tiles = (uint32_t)std::min<uint64_t>(L.max_tiles_large, (uint64_t)(n + T - 1) / T + n / (kSmallCap + 1) + 1);
         for (int i = 0; i < np; ++i) {
@@ -646,8 +645,7 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
             da.status_next = (i + 1 < np) ? S[(q + 1) % 2] : nullptr;
             da.tile_counter = ctl + kCtlPassCnt + kPassCounters * q;
             da.large_ctl = large_ctl;
-            da.large = large;
-            da.tile_map = tile_map;
+            da.tile_map = reinterpret_cast<const uint32_t*>(tile_geo);
             da.err = ctl + kCtlErr;
             QSD_CK(timed(kDigitSeg, 0, stream, [&] { return launch_digit(da, p.r, p.crd_bytes, p.val_bytes, plan->items, stream); }));
             cur = dst;

@@ -38,10 +38,6 @@ struct DevKey {
     int32_t dst[8];
 };
 
-struct SegRec {
-    uint32_t start, len, tile_base, pad;
-};
-
 // Items per thread of the digit pass (8 or 16): a whole record per item lives in registers,
 // so wide records take fewer items.  `pref` (0 = automatic) is a tuning override.
 inline int digit_items(int r, int crd_bytes, int val_bytes, int pref = 0) {
@@ -99,10 +95,10 @@ struct DigitArgs {
     uint32_t* status_next;      // zeroed for the next pass (may be null)
     uint32_t* tile_counter;     // kPassCounters tile queues (one queue below 2048 tiles)
     const uint64_t* large_ctl;  // segment mode
-    const SegRec* large;        // segment mode
-    const uint32_t* tile_map;   // segment mode: large segment of every tile; batch mode: four
-                                // words per launch tile (stable tile id, tensor, first record,
-                                // records), 16-byte aligned
+    const uint32_t* tile_map;   // four words per tile, 16-byte aligned.  Segment mode: first
+                                // record, records, the segment's first tile, large segment;
+                                // batch mode, per launch tile: stable tile id, tensor, first
+                                // record, records
     const BatchPass* batch;     // batch mode: this launch's table
     uint32_t* err;
     // Packed records (global and batch modes).  pk = 1: read the r coordinate arrays, write one
@@ -164,8 +160,7 @@ struct HistArgs {
     uint32_t* status_zero;      // status words of the first pass, zeroed here
     uint32_t status_words;      // global mode: words to zero
     const uint64_t* large_ctl;
-    const SegRec* large;
-    const uint32_t* tile_map;
+    const uint4* tile_geo;      // segment mode: as written by k_classify
 };
 
 struct BoundArgs {
@@ -198,8 +193,8 @@ struct ClassArgs {
     const uint32_t* region_seg;
     uint32_t nregions;
     uint64_t* large_ctl;
-    SegRec* large;
-    uint32_t* tile_map;
+    uint4* tile_geo;            // per large-segment tile: first record, records, the segment's
+                                // first tile, large segment
     uint32_t* seg_hist;         // zeroed per large segment
     uint32_t hist_stride;
 };
@@ -243,6 +238,8 @@ hipError_t launch_digit_batch(const DigitArgs& a, int rmax, int crd_bytes, int v
 hipError_t launch_hist_batch(const BatchHistArgs& a, int rmax, int crd_bytes, int grid, hipStream_t s);
 // counts -> exclusive prefix, in place, for `blocks` consecutive blocks of 256 words
 hipError_t launch_hist_prefix(uint32_t* hist, uint32_t blocks, hipStream_t s);
+hipError_t launch_hist_prefix_seg(uint32_t* hist, const uint64_t* large_ctl, uint32_t rows_per_seg,
+                                  uint32_t max_rows, hipStream_t s);
 hipError_t launch_small_batch(const BatchSmallJob* jobs, uint32_t njobs, int rmax, int crd_bytes,
                               int val_bytes, hipStream_t s);
 hipError_t launch_boundary(const BoundArgs& a, int crd_bytes, hipStream_t s);

@@ -154,6 +154,14 @@ hipError_t launch_hist_prefix(uint32_t* hist, uint32_t blocks, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_hist_prefix_seg(uint32_t* hist, const uint64_t* large_ctl, uint32_t rows_per_seg,
+                                  uint32_t max_rows, hipStream_t s) {
+    if (!max_rows) return hipSuccess;
+    const uint32_t grid = std::min<uint32_t>(max_rows, (uint32_t)device_cu_count() * 8);
+    hipLaunchKernelGGL(k_hist_prefix_seg, dim3(grid), dim3(kBlock), 0, s, hist, large_ctl, rows_per_seg);
+    return hipGetLastError();
+}
+
 template <typename CT, typename VT>
 hipError_t small_batch_cv(const BatchSmallJob* jobs, uint32_t njobs, int rmax, hipStream_t s) {
     const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(njobs, (uint32_t)device_cu_count() * 8));

@@ -290,7 +290,8 @@ __global__ void __launch_bounds__(256, 8) k_hist(HistArgs a) {
     const uint32_t t0 = blockIdx.x * per, t1 = min(nT, t0 + per);
     uint32_t cur = 0xFFFFFFFFu;
     for (uint32_t t = t0; t < t1; ++t) {
-        const uint32_t k = a.tile_map[t];
+        const uint4 g = a.tile_geo[t];  // first record, records, segment's first tile, segment
+        const uint32_t k = g.w;
         if (k != cur) {
             sync_after_lds_atomics();
             if (cur != 0xFFFFFFFFu) {
@@ -303,10 +304,7 @@ __global__ void __launch_bounds__(256, 8) k_hist(HistArgs a) {
             cur = k;
             __syncthreads();
         }
-        const SegRec s = a.large[k];
-        const uint32_t start = s.start + (t - s.tile_base) * a.tile;
-        const uint32_t end = min(s.start + s.len, start + a.tile);
-        count_range(start, end);
+        count_range(g.x, g.x + g.y);
         a.status_zero[(size_t)t * kBins + tid] = 0;
     }
     sync_after_lds_atomics();
@@ -492,6 +490,8 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (MODE == 0) s_hpre[tid] = block_excl_scan(a.hist[tid], s_tmp, nullptr);  // same for every tile
+    // segment mode: tiles of the large segments, written by the previous kernel
+    const uint32_t seg_tiles = MODE == 1 ? (uint32_t)*a.large_ctl : 0u;
 
     for (;;) {
         if (tid < 64) {
@@ -500,7 +500,7 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
             // each queue's tiles go out in increasing order, and a tile waits only for lower
             // tiles, so the lowest unfinished tile always has a running workgroup or a free one
             // that will take it.  Wave 0 computes the geometry (lane 0 takes the tile).
-            const uint32_t G = a.ntiles >= kQueueMinTiles ? min(kTileQueues, gridDim.x) : 1u;
+            const uint32_t G = (MODE == 1 ? seg_tiles : a.ntiles) >= kQueueMinTiles ? min(kTileQueues, gridDim.x) : 1u;
             const uint32_t qi = blockIdx.x % G;
             uint32_t taken = 0;
             if (tid == 0) taken = atomicAdd(a.tile_counter + qi, 1u);
@@ -508,15 +508,16 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
             uint32_t t = lt, ntiles = a.ntiles, start = 0, len = 0, base = 0, k = 0, lowest = 0;
             bool live = false;
             if (MODE == 1) {
-                ntiles = (uint32_t)*a.large_ctl;  // a.ntiles: the host's upper bound
+                ntiles = seg_tiles;
                 t = ((lt / kTileChunk) * G + qi) * kTileChunk + lt % kTileChunk;
                 if (t < ntiles) {
-                    k = a.tile_map[t];
-                    const SegRec s = a.large[k];
-                    base = s.start;
-                    lowest = s.tile_base;
-                    start = s.start + (t - s.tile_base) * TILE;
-                    len = min((uint32_t)TILE, s.start + s.len - start);
+                    // one load: first record, records, the segment's first tile, segment
+                    const uint4 g = reinterpret_cast<const uint4*>(a.tile_map)[t];
+                    start = g.x;
+                    len = g.y;
+                    lowest = g.z;
+                    k = g.w;
+                    base = start - (t - lowest) * TILE;
                     live = true;
                 }
             } else if (MODE == 2) {
@@ -706,10 +707,9 @@ __device__ __forceinline__ void digit_body(const DigitArgs& a) {
             }
             load_items<VT, ITEMS>((const VT*)src_val, start, len, wb, v);
             tstart = block_excl_scan(tcnt, s_tmp, nullptr);
-            // one segment: computed once per workgroup; batch: offsets stored by k_hist_prefix
-            hstart = MODE == 0   ? s_hpre[b]
-                     : MODE == 2 ? hist[b]
-                                 : block_excl_scan(hist[b], s_tmp + kWaves, nullptr);
+            // one sort: computed once per workgroup; segments and batches: offsets stored by
+            // k_hist_prefix_seg / k_hist_prefix
+            hstart = MODE == 0 ? s_hpre[b] : hist[b];
             s_tstart[b] = tstart;
         }
         // ---- the global offset of every digit: decoupled look-back over the predecessors
@@ -914,14 +914,9 @@ __global__ void __launch_bounds__(256) k_classify(ClassArgs a) {
             const uint32_t tiles = (len + a.tile - 1) / a.tile;
             const unsigned long long old =
                 atomicAdd((unsigned long long*)a.large_ctl, (1ull << 32) | (unsigned long long)tiles);
-            const uint32_t idx = (uint32_t)(old >> 32);
-            SegRec rec;
-            rec.start = s;
-            rec.len = len;
-            rec.tile_base = (uint32_t)old;
-            rec.pad = 0;
-            a.large[idx] = rec;
-            for (uint32_t i = 0; i < tiles; ++i) a.tile_map[rec.tile_base + i] = idx;
+            const uint32_t idx = (uint32_t)(old >> 32), tile_base = (uint32_t)old;
+            for (uint32_t i = 0; i < tiles; ++i)
+                a.tile_geo[tile_base + i] = make_uint4(s + i * a.tile, min(a.tile, len - i * a.tile), tile_base, idx);
             uint32_t* h = a.seg_hist + (size_t)idx * a.hist_stride;
             for (uint32_t i = 0; i < a.hist_stride; ++i) h[i] = 0;
         }
@@ -1387,6 +1382,19 @@ __global__ void __launch_bounds__(256) k_hist_prefix(uint32_t* hist) {
     uint32_t* h = hist + (size_t)blockIdx.x * kBins;
     const uint32_t c = h[threadIdx.x];
     h[threadIdx.x] = block_excl_scan(c, s_tmp, nullptr);
+}
+
+// The same for the per-segment blocks of a segmented group: rows_per_seg blocks (one per pass)
+// for every large segment that k_classify found.
+__global__ void __launch_bounds__(256) k_hist_prefix_seg(uint32_t* hist, const uint64_t* large_ctl, uint32_t rows_per_seg) {
+    __shared__ uint32_t s_tmp[kWaves];
+    const uint32_t rows = (uint32_t)(*large_ctl >> 32) * rows_per_seg;
+    for (uint32_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        uint32_t* h = hist + (size_t)row * kBins;
+        const uint32_t c = h[threadIdx.x];
+        h[threadIdx.x] = block_excl_scan(c, s_tmp, nullptr);
+        __syncthreads();  // s_tmp is reused by the next row
+    }
 }
 
 // One small tensor per workgroup, sorted entirely in LDS by its flattened key: LSD passes
