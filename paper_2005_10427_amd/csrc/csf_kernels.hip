@@ -9,28 +9,6 @@ namespace {
 
 // ------------------------------------------------------------------------------ CSF pack
 
-// The value of the lane below, for 32- or 64-bit values (lane 0 receives ~0).
-template <typename CT>
-__device__ __forceinline__ CT csf_lane_below(CT x) {
-    if constexpr (sizeof(CT) == 8) {
-        const uint64_t lo = from_lane_below((uint32_t)x), hi = from_lane_below((uint32_t)((uint64_t)x >> 32));
-        return (CT)((hi << 32) | lo);
-    } else {
-        return (CT)from_lane_below((uint32_t)x);
-    }
-}
-// The value held by lane 63 (uniform).
-template <typename CT>
-__device__ __forceinline__ CT csf_lane63(CT x) {
-    if constexpr (sizeof(CT) == 8) {
-        const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
-        const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), 63);
-        return (CT)((hi << 32) | lo);
-    } else {
-        return (CT)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
-    }
-}
-
 // CSF of n records sorted under sigma, given in level order.  Record j starts a level-d fiber
 // (1-based d < R) when its prefix sigma_1..sigma_d differs from record j-1's, i.e. when the
 // first level lev(j) at which its coordinates differ is below d (record 0 starts every level);
@@ -87,9 +65,9 @@ __global__ void __launch_bounds__(256) k_csf(CsfArgs a) {
             CT carry = has_prev ? ((const CT*)a.crd[d])[start + w0 - 1] : CT(0);
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
-                const CT below = csf_lane_below(x[d][i]);
+                const CT below = lane_below(x[d][i]);
                 const CT prv = lane == 0 ? carry : below;
-                carry = csf_lane63(x[d][i]);
+                carry = lane63(x[d][i]);
                 if (x[d][i] != prv) lev[i] = (uint32_t)d;
             }
         }

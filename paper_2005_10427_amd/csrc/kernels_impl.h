@@ -52,6 +52,28 @@ __device__ __forceinline__ void sync_after_lds_atomics() {
 __device__ __forceinline__ uint32_t from_lane_below(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
 }
+// The value of the lane below, for 32- or 64-bit values (lane 0 receives ~0).
+template <typename CT>
+__device__ __forceinline__ CT lane_below(CT x) {
+    if constexpr (sizeof(CT) == 8) {
+        const uint64_t lo = from_lane_below((uint32_t)x), hi = from_lane_below((uint32_t)((uint64_t)x >> 32));
+        return (CT)((hi << 32) | lo);
+    } else {
+        return (CT)from_lane_below((uint32_t)x);
+    }
+}
+// The value held by lane 63 (uniform).
+template <typename CT>
+__device__ __forceinline__ CT lane63(CT x) {
+    if constexpr (sizeof(CT) == 8) {
+        const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+        const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), 63);
+        return (CT)((hi << 32) | lo);
+    } else {
+        return (CT)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+    }
+}
+
 // Values that are the same in every lane, moved into scalar registers.
 __device__ __forceinline__ uint32_t uni32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 __device__ __forceinline__ uint64_t uni64(uint64_t v) {
@@ -830,19 +852,23 @@ __global__ void __launch_bounds__(256) k_boundary(BoundArgs a) {
             f[i] |= ((w >> lane) & 1ull) != 0;
         }
     }
-    for (int j = a.prev_bits ? a.nskip : 0; j < a.nprefix; ++j) {  // all loads of one prefix mode in flight together
+    // one prefix mode at a time, all of its loads in flight together (range-checked: 0 past
+    // the tile); each record's predecessor comes from the lane below, from lane 63 of the
+    // previous item, or, for the wave's first record, from one scalar load
+    const uint32_t wfirst = (uint32_t)wave * 64u * ITEMS;
+    const bool has_prev = wfirst < len && start + wfirst > 0;
+    for (int j = a.prev_bits ? a.nskip : 0; j < a.nprefix; ++j) {
         const CT* p = (const CT*)a.crd[a.prefix[j]];
-        CT cur[ITEMS], prv[ITEMS];
+        CT cur[ITEMS];
+        load_items<CT, ITEMS>(p, start, len, wb, cur);
+        CT carry = has_prev ? p[start + wfirst - 1] : CT(0);
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t off = wb + i * 64;
-            const uint32_t e = start + off;
-            const bool ok = off < len && e > 0;
-            cur[i] = ok ? p[e] : CT(0);
-            prv[i] = ok ? p[e - 1] : CT(0);
+            const CT below = lane_below(cur[i]);
+            const CT prv = lane == 0 ? carry : below;
+            carry = lane63(cur[i]);
+            f[i] |= cur[i] != prv;
         }
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) f[i] |= cur[i] != prv[i];
     }
     uint32_t wcount = 0;
 #pragma unroll
