@@ -9,6 +9,11 @@ Also reported: the roofline of the dominant kernel (the digit pass), timed with 
 recorded by the library on the stream each launch runs on, and the CPU oracle timed on a
 bounded sample of the same workload.
 
+``--workload wide``: the 4-mode tensor with extents 1000000 x 100000 x 1000 x 50, 2e8
+distinct nonzeros (modes 0-1 Zipf(1.3), modes 2-3 uniform), int32 coordinates, fp32 values,
+input order (0,1,2,3), transposed to all 23 other orders per step (the plans with bucketed
+groups run the segment sorts).
+
 ``--workload batched``: 4,096 independent tensors (order 3 or 4, nnz log-uniform in
 [1e3, 1e6], extents log-uniform in [10, 1e6], Zipf exponents uniform in [0, 1.5], fp64
 values, random input and requested orders); one step is one replay of the autotuned,
@@ -112,7 +117,7 @@ def main():
                     help="run bucketed groups as segment sorts (QSD_KEEP_BUCKETS) instead of flattening")
     ap.add_argument("--nnz", type=int, default=None, help="shrink the workload (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="plain", choices=["plain", "batched"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "wide", "batched"])
     ap.add_argument("--count", type=int, default=None, help="tensors of the batched workload (testing only)")
     ap.add_argument("--no-sequence", action="store_true",
                     help="batched workload: skip timing the one-by-one comparison (for profiler runs)")
@@ -136,25 +141,30 @@ def main():
         return 1
     if args.workload == "batched":
         return bench_batched(args)
-    cfg = CONFIGS["plain"]
+    name = args.workload
+    cfg = CONFIGS[name]
     sigmas = cfg["sigmas"]
-    log("generating workload ...")
+    log(f"generating the {name} workload ...")
     t0 = time.time()
-    T = config_tensor("plain", nnz=args.nnz)
+    T = config_tensor(name, nnz=args.nnz)
     N = T.nnz
     log(f"generated {N} nonzeros in {time.time() - t0:.1f} s")
+    ct, vt = str(T.crd[0].dtype), str(T.val.dtype)
 
     dev = torch.device("cuda:0")
     crd = [torch.from_numpy(c).to(dev) for c in T.crd]
     val = torch.from_numpy(T.val).to(dev)
     model = qsd.qsd_model_load(qsd.MODEL_PATH) if args.sched == "auto" else None
     flags = qsd.QSD_KEEP_BUCKETS if args.keep_buckets else 0
-    plans = [qsd.Plan(T.extents, T.in_order, s, N, "int32", "float64", args.sched, flags, model=model, crd=crd)
+    plans = [qsd.Plan(T.extents, T.in_order, s, N, ct, vt, args.sched, flags, model=model, crd=crd)
              for s in sigmas]
     if model is not None:
         log("selector chose " + ", ".join(f"{s}: {qsd.CAND_NAMES[p.chosen]}" for s, p in zip(sigmas, plans)))
     ws = torch.empty(max(p.ws_bytes for p in plans), dtype=torch.uint8, device=dev)
-    outs = [([torch.empty_like(c) for c in crd], torch.empty_like(val)) for _ in sigmas]
+    if name == "plain":
+        outs = [([torch.empty_like(c) for c in crd], torch.empty_like(val)) for _ in sigmas]
+    else:  # 23 orders: one output set, overwritten by every order in turn
+        outs = [([torch.empty_like(c) for c in crd], torch.empty_like(val))] * len(sigmas)
     stream = torch.cuda.current_stream(dev)
 
     def step():
@@ -196,7 +206,7 @@ def main():
     avg_s = ms / n_l / 1e3
     bytes_per_launch = b / n_l
     achieved = bytes_per_launch / avg_s / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic() if name == "plain" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_digit (global digit pass)", "launches": n_l,
@@ -207,9 +217,12 @@ def main():
         "metric": METRIC, "value": value, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": "plain: 3-mode COO 500000x20000x2000000, 1e8 distinct nonzeros, "
-                               "Zipf(1.1) coordinates, int32 coordinates, fp64 values, input order "
-                               "(0,1,2) -> all 5 other orders per step",
+        "config": {"workload": ("plain: 3-mode COO 500000x20000x2000000, 1e8 distinct nonzeros, "
+                                "Zipf(1.1) coordinates, int32 coordinates, fp64 values, input order "
+                                "(0,1,2) -> all 5 other orders per step") if name == "plain" else
+                               ("wide: 4-mode COO 1000000x100000x1000x50, 2e8 distinct nonzeros, "
+                                "Zipf(1.3) on modes 0-1, uniform modes 2-3, int32 coordinates, fp32 "
+                                "values, input order (0,1,2,3) -> all 23 other orders per step"),
                    "nnz": N, "orders": [list(s) for s in sigmas], "schedule": args.sched,
                    "bucketed_groups": "segment sorts" if args.keep_buckets else "flattened where cheaper"},
         "roofline": roofline,
@@ -217,7 +230,7 @@ def main():
     }
     # CSF pack of the last order's output (reported beside the metric, not part of it)
     csf = None
-    if outs:
+    if outs and name == "plain":
         P = plans[-1]
         oc = outs[-1][0]
         P.pack_csf(oc)  # warm-up (allocates its outputs)
@@ -232,13 +245,13 @@ def main():
         log(f"CSF pack of sigma={sigmas[-1]}: {sec * 1e3:.3f} ms, fibers {counts}")
     out["csf_pack"] = csf
     if args.copy_probe:
-        ident = qsd.Plan(T.extents, T.in_order, T.in_order, N, "int32", "float64", args.sched)
+        ident = qsd.Plan(T.extents, T.in_order, T.in_order, N, ct, vt, args.sched)
         oc, ov = outs[0]
         for _ in range(args.copy_probe):
             ident.transpose(crd, val, oc, ov, stream=stream, ws=ws)
         torch.cuda.synchronize()
         out["copy_probe"] = {"launches_per_call": T.order + 1,
-                             "bytes_per_crd_copy": 2 * N * 4, "bytes_per_val_copy": 2 * N * 8}
+                             "bytes_per_crd_copy": 2 * N * T.crd[0].itemsize, "bytes_per_val_copy": 2 * N * T.val.itemsize}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(T, sigmas)
