@@ -61,8 +61,8 @@ namespace {
 // A global group of two or more digit passes moves packed records when every coordinate of a
 // nonzero fits in one 64-bit word: the first pass packs, the last unpacks (Sec. 5's bit
 // packing).  The group's composite key occupies the low bits of the word.
-bool packable(const qsd_plan_s* q, const Group& g) {
-    if (!q->pack || g.segmented || g.subs.size() != 1 || g.subs[0].passes.size() < 2) return false;
+bool packable_key(const qsd_plan_s* q, const Group& g) {
+    if (!q->pack || g.subs.size() != 1 || g.subs[0].passes.size() < 2) return false;
     int total = 0;
     for (int m = 0; m < q->p.r; ++m) total += q->p.bits[m];
     if (total > 64) return false;
@@ -71,6 +71,10 @@ bool packable(const qsd_plan_s* q, const Group& g) {
         if (k.width[m] && (k.src_lo[m] != 0 || k.width[m] != q->p.bits[m])) return false;
     return true;
 }
+bool packable(const qsd_plan_s* q, const Group& g) { return !g.segmented && packable_key(q, g); }
+// The large segments of a segmented group take the same packed passes (kernels for 16 records
+// per thread only); the LDS segment sorts move the records as they are.
+bool packable_seg(const qsd_plan_s* q, const Group& g) { return g.segmented && q->items == 16 && packable_key(q, g); }
 
 // Word layout of packed records: key modes at their place in the composite key (low bits),
 // the other modes above it.
@@ -170,7 +174,7 @@ void make_layout(qsd_plan_s* q) {
         at = up(at + cdiv(N, 64) * 8);
     }
     bool any_pack = false;
-    for (const auto& g : p.groups) any_pack |= packable(q, g);
+    for (const auto& g : p.groups) any_pack |= packable(q, g) || packable_seg(q, g);
     if (any_pack)
         for (int i = 0; i < 2; ++i) {
             L.pk[i] = at;
@@ -624,16 +628,36 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
             return launch_hist_prefix_seg(seg_hist, large_ctl, (uint32_t)np, L.max_large * (uint32_t)np, stream);
         }));
         const uint32_t max_tiles = (uint32_t)std::min<uint64_t>(L.max_tiles_large, (uint64_t)(n + T - 1) / T + n / (kSmallCap + 1) + 1);
+        const bool spk = packable_seg(plan, g);
+        void* P[2] = {W + L.pk[0], W + L.pk[1]};
         for (int i = 0; i < np; ++i) {
             const Bufs dst = hop_dst(h);
             DigitArgs da{};
+            int r_launch = p.r, cb_launch = p.crd_bytes;
             for (int m = 0; m < p.r; ++m) {
                 da.src_crd[m] = cur.crd[m];
                 da.dst_crd[m] = const_cast<void*>(dst.crd[m]);
             }
+            da.key = key;
+            if (spk) {  // as in a global group: the first pass packs, the last unpacks
+                pack_spec(p, sk.key, da);
+                if (i == 0) {
+                    da.pk = 1;
+                    da.dst_crd[0] = P[0];
+                } else if (i + 1 < np) {  // packed words in and out: one 64-bit "mode"
+                    da = DigitArgs{};
+                    da.src_crd[0] = P[(i - 1) % 2];
+                    da.dst_crd[0] = P[i % 2];
+                    da.key.mask[0] = sk.key.bits >= 64 ? ~0ull : ((1ull << sk.key.bits) - 1);
+                    r_launch = 1;
+                    cb_launch = 8;
+                } else {
+                    da.pk = 2;
+                    da.src_crd[0] = P[(i - 1) % 2];
+                }
+            }
             da.src_val = cur.val;
             da.dst_val = const_cast<void*>(dst.val);
-            da.key = key;
             da.lo = sk.passes[i].lo;
             da.bits = sk.passes[i].bits;
             da.n = n;
@@ -647,7 +671,7 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
             da.large_ctl = large_ctl;
             da.tile_map = reinterpret_cast<const uint32_t*>(tile_geo);
             da.err = ctl + kCtlErr;
-            QSD_CK(timed(kDigitSeg, 0, stream, [&] { return launch_digit(da, p.r, p.crd_bytes, p.val_bytes, plan->items, stream); }));
+            QSD_CK(timed(kDigitSeg, 0, stream, [&] { return launch_digit(da, r_launch, cb_launch, p.val_bytes, plan->items, stream); }));
             cur = dst;
             ++h;
             ++q;

@@ -490,11 +490,10 @@ __device__ __forceinline__ void drain_items(const T* sx, T* __restrict__ dst, ui
 
 // MODE 0: one segment [0, n).  MODE 1: the large segments of a bucketed group.  MODE 2: a
 // batch of tensors (each tensor is one segment; its parameters come from a device table).
-// PK (MODE 0 only): 0 records as given; 1 pack the R coordinate arrays into one array of
-// 64-bit words on the way out; 2 unpack such words into R coordinate arrays.
+// PK: 0 records as given; 1 pack the R coordinate arrays into one array of 64-bit words on the
+// way out; 2 unpack such words into R coordinate arrays.
 template <int R, typename CT, typename VT, int ITEMS, int MODE, int PK>
 __device__ __forceinline__ void digit_body(const DigitArgs& a) {
-    static_assert(PK == 0 || MODE != 1, "packed records are a global or batch layout");
     constexpr bool PACK = PK == 1, UNPACK = PK == 2;
     constexpr int TILE = kBlock * ITEMS;
     __shared__ uint64_t s_x[TILE];               // record exchange (4- or 8-byte words)
@@ -1650,7 +1649,15 @@ hipError_t digit_ri(const DigitArgs& a, hipStream_t s) {
         if (a.pk == 2) return digit_rs<R, CT, VT, ITEMS, 2, 2>(a, s);
         return digit_rs<R, CT, VT, ITEMS, 2>(a, s);
     }
-    if (a.seg_mode == 1) return digit_rs<R, CT, VT, ITEMS, 1>(a, s);
+    if (a.seg_mode == 1) {
+        if constexpr (ITEMS == 16) {  // packed segment passes: 16 records per thread only
+            if (a.pk == 1) return digit_rs<R, CT, VT, ITEMS, 1, 1>(a, s);
+            if (a.pk == 2) return digit_rs<R, CT, VT, ITEMS, 1, 2>(a, s);
+        } else {
+            if (a.pk) return hipErrorInvalidValue;
+        }
+        return digit_rs<R, CT, VT, ITEMS, 1>(a, s);
+    }
     if (a.pk == 1) return digit_rs<R, CT, VT, ITEMS, 0, 1>(a, s);
     if (a.pk == 2) return digit_rs<R, CT, VT, ITEMS, 0, 2>(a, s);
     return digit_rs<R, CT, VT, ITEMS, 0>(a, s);
