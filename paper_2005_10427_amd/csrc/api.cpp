@@ -149,7 +149,7 @@ void make_layout(qsd_plan_s* q) {
         at = up(at + (cdiv(N, kRegion) + 2) * 4);
         L.tile_map = at;
         at = up(at + (size_t)L.max_tiles_large * 16);
-        L.bstatus_words = cdiv(N, kBoundTile);
+        L.bstatus_words = cdiv(N, kDiscTile);
         L.bstatus = at;
         at = up(at + L.bstatus_words * 4 * q->nseg_groups);
         L.geo = at;

@@ -13,6 +13,7 @@ constexpr int kSmallCap = 4096;    // records one workgroup sorts in LDS
 constexpr int kTinyLen = 2048;     // segments up to this length are packed by region
 constexpr int kRegion = 2048;      // region width for packing tiny segments
 constexpr int kBoundTile = 4096;   // elements per tile of the boundary scan
+constexpr int kDiscTile = 32768;   // records per tile of bucket discovery
 constexpr int kCtlWords = 1024;    // control block (counters, sizes, flags), 4 KB
 
 // control block word offsets (uint32 unless noted)

@@ -84,7 +84,7 @@ hipError_t launch_digit(const DigitArgs& a, int r, int crd_bytes, int val_bytes,
 }
 
 hipError_t launch_boundary(const BoundArgs& a, int crd_bytes, hipStream_t s) {
-    const uint32_t grid = (a.n + kBoundTile - 1) / kBoundTile;
+    const uint32_t grid = (a.n + kDiscTile - 1) / kDiscTile;
     if (!grid) return hipSuccess;
     if (crd_bytes == 8)
         hipLaunchKernelGGL(k_boundary<uint64_t>, dim3(grid), dim3(kBlock), 0, s, a);

@@ -821,10 +821,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
 // ------------------------------------------------------------------------------ buckets
 
 // Segment starts: positions where the prefix (sigma_1..sigma_l) differs from the previous
-// record (Alg. 2's bucket discovery), compacted in order with a single-word look-back.
+// record (Alg. 2's bucket discovery), compacted in order with a single-word look-back.  The work
+// per record is tiny, so tiles are large (kDiscTile records, eight sub-chunks per wave whose
+// 64-record flag masks wait in LDS): with 4096-record tiles, thousands of tiles were in flight
+// at once and each look-back found the nearest published prefix far behind it, 64 tiles per
+// memory round trip, which bounded the whole kernel.
 template <typename CT>
 __global__ void __launch_bounds__(256) k_boundary(BoundArgs a) {
-    constexpr int ITEMS = kBoundTile / kBlock;
+    constexpr int SUB = 16;                               // 64-record items per wave and sub-chunk
+    constexpr int WSPAN = kDiscTile / kWaves;             // records of one wave
+    constexpr int NSUB = WSPAN / (SUB * 64);
+    constexpr int NP = sizeof(BoundArgs::prefix) / sizeof(int32_t);  // prefix modes at most
+    static_assert(NSUB * SUB * 64 * kWaves == kDiscTile, "tile shape");
+    __shared__ uint64_t s_mask[kDiscTile / 64];           // flags, one word per 64 records
     __shared__ uint32_t s_wsum[kWaves];
     __shared__ uint32_t s_geo[2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -834,52 +843,58 @@ __global__ void __launch_bounds__(256) k_boundary(BoundArgs a) {
     }
     __syncthreads();
     const uint32_t t = s_geo[0];
-    const uint32_t start = t * kBoundTile;
+    const uint32_t start = t * kDiscTile;
     if (start >= a.n) return;
-    const uint32_t len = min((uint32_t)kBoundTile, a.n - start);
-    const uint32_t wb = (uint32_t)wave * 64u * ITEMS + lane;
-    uint64_t flags[ITEMS];
-    bool f[ITEMS];
+    const uint32_t len = min((uint32_t)kDiscTile, a.n - start);
+    const uint32_t w0 = (uint32_t)wave * WSPAN;           // the wave's first record in the tile
+    const int j0 = a.prev_bits ? a.nskip : 0;
+    // the previous record of each prefix mode: for the wave's first record one scalar load,
+    // then lane 63 of the item before
+    CT carry[NP];
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) f[i] = (start + wb + i * 64 == 0);
-    if (a.prev_bits) {  // the previous group's segment starts: one word per 64 records
-        const uint32_t w0 = (start + (uint32_t)wave * 64u * ITEMS) / 64u;
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t off = wb + i * 64;
-            const uint64_t w = off < len ? a.prev_bits[w0 + i] : 0ull;
-            f[i] |= ((w >> lane) & 1ull) != 0;
-        }
-    }
-    // one prefix mode at a time, all of its loads in flight together (range-checked: 0 past
-    // the tile); each record's predecessor comes from the lane below, from lane 63 of the
-    // previous item, or, for the wave's first record, from one scalar load
-    const uint32_t wfirst = (uint32_t)wave * 64u * ITEMS;
-    const bool has_prev = wfirst < len && start + wfirst > 0;
-    for (int j = a.prev_bits ? a.nskip : 0; j < a.nprefix; ++j) {
-        const CT* p = (const CT*)a.crd[a.prefix[j]];
-        CT cur[ITEMS];
-        load_items<CT, ITEMS>(p, start, len, wb, cur);
-        CT carry = has_prev ? p[start + wfirst - 1] : CT(0);
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const CT below = lane_below(cur[i]);
-            const CT prv = lane == 0 ? carry : below;
-            carry = lane63(cur[i]);
-            f[i] |= cur[i] != prv;
-        }
+    for (int j = 0; j < NP; ++j) {
+        carry[j] = CT(0);
+        if (j >= j0 && j < a.nprefix && w0 < len && start + w0 > 0) carry[j] = ((const CT*)a.crd[a.prefix[j]])[start + w0 - 1];
     }
     uint32_t wcount = 0;
+    for (int k = 0; k < NSUB; ++k) {
+        const uint32_t o0 = w0 + (uint32_t)k * SUB * 64;  // sub-chunk's first record in the tile
+        bool f[SUB];
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        flags[i] = ballot(f[i] && (wb + i * 64 < len));
-        wcount += (uint32_t)__popcll(flags[i]);
-    }
-    if (a.bits_out && lane == 0) {
-        const uint32_t w0 = (start + (uint32_t)wave * 64u * ITEMS) / 64u;
+        for (int i = 0; i < SUB; ++i) f[i] = (start + o0 + i * 64 + lane == 0);
+        if (a.prev_bits) {  // the previous group's segment starts: one word per 64 records
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i)
-            if ((uint32_t)wave * 64u * ITEMS + i * 64 < len) a.bits_out[w0 + i] = flags[i];
+            for (int i = 0; i < SUB; ++i) {
+                const uint64_t w = o0 + i * 64 < len ? a.prev_bits[(start + o0) / 64u + i] : 0ull;
+                f[i] |= ((w >> lane) & 1ull) != 0;
+            }
+        }
+        // one prefix mode at a time, all of its loads in flight together (range-checked: 0
+        // past the tile); each record's predecessor comes from the lane below or the carry
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            if (j >= j0 && j < a.nprefix) {
+                CT cur[SUB];
+                load_items<CT, SUB>((const CT*)a.crd[a.prefix[j]], start, len, o0 + lane, cur);
+#pragma unroll
+                for (int i = 0; i < SUB; ++i) {
+                    const CT below = lane_below(cur[i]);
+                    const CT prv = lane == 0 ? carry[j] : below;
+                    carry[j] = lane63(cur[i]);
+                    f[i] |= cur[i] != prv;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < SUB; ++i) {
+            const bool valid = o0 + i * 64 < len;
+            const uint64_t m = ballot(f[i] && o0 + i * 64 + lane < len);
+            wcount += (uint32_t)__popcll(m);
+            if (lane == 0) {
+                s_mask[o0 / 64 + i] = m;
+                if (a.bits_out && valid) a.bits_out[(start + o0) / 64u + i] = m;
+            }
+        }
     }
     if (lane == 0) s_wsum[wave] = wcount;
     __syncthreads();
@@ -902,13 +917,13 @@ __global__ void __launch_bounds__(256) k_boundary(BoundArgs a) {
     __syncthreads();
     uint32_t pos = s_geo[1];
     for (int w = 0; w < wave; ++w) pos += s_wsum[w];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint64_t f = flags[i];
-        const uint32_t e = start + wb + i * 64;
+    for (int q = 0; q < NSUB * SUB; ++q) {
+        const uint32_t o = w0 + (uint32_t)q * 64;
+        const uint64_t f = s_mask[o / 64];
+        const uint32_t e = start + o + lane;
         const uint32_t before = pos + lanes_below(f);  // segments starting before e
         if ((f >> lane) & 1ull) a.seg_start[before] = e;
-        if (wb + i * 64 < len && e % (uint32_t)kRegion == 0) a.region_seg[e / kRegion] = before;
+        if (o + lane < len && e % (uint32_t)kRegion == 0) a.region_seg[e / kRegion] = before;
         pos += (uint32_t)__popcll(f);
     }
 }
