@@ -77,7 +77,7 @@ typedef enum qsd_sched_t {
 /* Bucketed groups (PartialSort calls that keep a prefix, Alg. 2) always run as bucket
  * discovery plus segment-local sorts.  Without this flag, a bucketed group whose nonzeros pack
  * into one 64-bit word is run as one global sort on (prefix, keys) with packed records when
- * that adds at most two digit passes: the same stable result (the input is sorted on the
+ * that adds at most one digit pass: the same stable result (the input is sorted on the
  * prefix), usually cheaper. */
 #define QSD_KEEP_BUCKETS 2u
 

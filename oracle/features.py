@@ -36,7 +36,7 @@ Plan terms of a candidate: its groups (consecutive partial sorts that keep the s
 as the library runs them), with modes of extent 1 dropped from the keys; a bucketed group is
 run as one global sort on (prefix, keys) when its key is wider than 52 bits, or (candidate 0
 and the Top-K candidates) when every nonzero packs into 64 bits, the flattened key is at most
-64 bits and it needs at most two digit passes more than the key alone.  A key of B bits is
+64 bits and it needs at most one digit pass more than the key alone.  A key of B bits is
 cut into 64-bit sub-keys and each into ceil(b / 8) digit passes.
   gp  digit passes of the global groups;   sb  key bits of the bucketed groups.
 
@@ -161,7 +161,7 @@ def _run_groups(groups, bits, keep_buckets):
             continue
         pb = sum(bits[m] for m in pre)
         flat = kb > 52 or (not keep_buckets and total <= 64 and pb + kb <= 64 and
-                           -(-(pb + kb) // RADIX) <= -(-kb // RADIX) + 2)
+                           -(-(pb + kb) // RADIX) <= -(-kb // RADIX) + 1)
         if flat:
             gp += _passes(pb + kb)
         else:
@@ -221,7 +221,7 @@ def _same_execution(tau_in, sigma, bits):
             continue
         kb = sum(bits[m] for m in keys)
         pb = sum(bits[m] for m in pre)
-        if kb <= 52 and total <= 64 and pb + kb <= 64 and -(-(pb + kb) // RADIX) <= -(-kb // RADIX) + 2:
+        if kb <= 52 and total <= 64 and pb + kb <= 64 and -(-(pb + kb) // RADIX) <= -(-kb // RADIX) + 1:
             return False
     return True
 

@@ -105,7 +105,7 @@ class Timer:
         return out[0], out[1], best
 
 
-def collect(path, count, seed, big=False):
+def collect(path, count, seed, big=False, budget_s=None):
     import torch
     from datagen.batched import iter_batch, make_batch
     rows = {}
@@ -145,6 +145,9 @@ def collect(path, count, seed, big=False):
             if (i + 1) % 100 == 0:
                 save()
                 log(f"collected {len(rows['index'])} rows ({i + 1}/{count} tensors, {time.time() - t_start:.0f} s)")
+                if budget_s is not None and time.time() - t_start > budget_s:
+                    log(f"time budget of {budget_s:.0f} s used: stopping after tensor {i} (run again to resume)")
+                    return None
         if big and count not in done:
             log("generating the 1.5e8-nonzero 5-mode tensor ...")
             T = make_batch(0, seed=seed, device="cuda", extra=[BIG])[0]
@@ -318,6 +321,8 @@ def main(argv=None):
     ap.add_argument("--eval-count", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--no-big", action="store_true")
+    ap.add_argument("--budget-s", type=float, default=None,
+                    help="collect: stop (after a save) once this many seconds are spent; a later run resumes")
     ap.add_argument("--train-data", default=None, help="an existing collection to train on (skips collect)")
     args = ap.parse_args(argv)
     import torch
@@ -330,7 +335,8 @@ def main(argv=None):
     model = os.path.join(args.dir, "selector_model.bin")
     report = {}
     if args.cmd in ("collect", "all") and not args.train_data:
-        collect(data, args.count, TRAIN_SEED)
+        if collect(data, args.count, TRAIN_SEED, budget_s=args.budget_s) is None:
+            return 3  # unfinished: run again to resume
     if args.cmd in ("train", "all"):
         report["train"] = train([data], model, epochs=args.epochs)
     if args.cmd in ("evaluate", "all"):

@@ -156,17 +156,21 @@ def test_digit_split_covers_key_bits(lib):
 
 def test_bucketed_group_flattening_rule(lib):
     ext = [500000, 20000, 2000000]  # 19/15/21 bits: every nonzero packs into 55 bits
-    # (0,2,1): bucket prefix 0 (19 bits) over key 2 (21 bits): 3 key passes, 5 flattened
+    # (0,2,1): bucket prefix 0 (19 bits) over key 2 (21 bits): 3 key passes, 5 flattened, so
+    # the buckets are kept
     _, calls, groups = _plan(3, (0, 1, 2), (0, 2, 1), "minimal", extents=ext, flags=0)
     assert calls == [((0,), 2)]  # the PartialSort calls are Alg. 3's either way
-    assert groups == [dict(prefix="", keys="0,2", bits="40", passes="5", segmented="0")]
+    assert groups == [dict(prefix="0", keys="2", bits="21", passes="3", segmented="1")]
+    # a 3-mode case where the prefix adds one pass (10 + 10 bits: 2 key passes, 3 flattened)
+    _, _, groups = _plan(3, (0, 1, 2), (0, 2, 1), "minimal", extents=[1000, 800, 600], flags=0)
+    assert groups == [dict(prefix="", keys="0,2", bits="20", passes="3", segmented="0")]
     # a 4-mode case where the prefix would add three passes keeps its buckets
     ext4 = [1000000, 100000, 1000, 50]  # 20/17/10/6 bits
     _, _, groups = _plan(4, (0, 1, 2, 3), (0, 1, 3, 2), "minimal", extents=ext4, flags=0)
     assert groups[0]["segmented"] == "1" and groups[0]["prefix"] == "0,1"
-    # a 4-mode case where it adds two: flattened
+    # a 4-mode case where it adds two: buckets kept too
     _, _, groups = _plan(4, (0, 1, 2, 3), (0, 2, 1, 3), "minimal", extents=ext4, flags=0)
-    assert groups[0]["segmented"] == "0" and groups[0]["keys"] == "0,2"
+    assert groups[0]["segmented"] == "1" and groups[0]["prefix"] == "0"
     # too wide to pack (int32 extents summing past 64 bits): buckets kept
     _, _, groups = _plan(4, (0, 1, 2, 3), (0, 2, 1, 3), "minimal", extents=[1 << 20, 1 << 20, 1 << 20, 1 << 10],
                          flags=0)
