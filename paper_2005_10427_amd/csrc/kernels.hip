@@ -101,8 +101,10 @@ hipError_t launch_classify(const ClassArgs& a, uint32_t max_segments, hipStream_
 
 template <typename CT, typename VT>
 hipError_t small_cv(const SmallArgs& a, uint32_t grid, hipStream_t s) {
-#define QSD_SMALL_CASE(RR) \
-    case RR: hipLaunchKernelGGL((k_small<RR, CT, VT>), dim3(grid), dim3(kBlock), 0, s, a); break;
+#define QSD_SMALL_CASE(RR)                                                                                  \
+    case RR:                                                                                                \
+        hipLaunchKernelGGL((k_small<RR, CT, VT, small_waves<RR, CT, VT>()>), dim3(grid), dim3(kBlock), 0, s, a); \
+        break;
     switch (a.r) {
         QSD_SMALL_CASE(1) QSD_SMALL_CASE(2) QSD_SMALL_CASE(3) QSD_SMALL_CASE(4)
         QSD_SMALL_CASE(5) QSD_SMALL_CASE(6) QSD_SMALL_CASE(7) QSD_SMALL_CASE(8)

@@ -1003,8 +1003,8 @@ __device__ __forceinline__ void buf_st(T v, __amdgpu_buffer_rsrc_t r, int off) {
 // positions of the destination, which may be the source itself.  With no records held in
 // registers and 26 KB of LDS, several runs share a CU; the next item's geometry is loaded one
 // item ahead.
-template <int R, typename CT, typename VT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_small(SmallArgs a) {
+template <int R, typename CT, typename VT, int W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) k_small(SmallArgs a) {
     constexpr int CAP = kSmallCap, ITEMS = CAP / kBlock;
     static_assert(kTinyLen == kRegion && kRegion + kTinyLen <= kSmallCap, "a region run must fit");
     __shared__ uint16_t s_ia[CAP], s_ib[CAP];  // slot permutations; s_ib first holds segment numbers
@@ -1272,6 +1272,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
         __syncthreads();
     }
 }
+
+// W resident waves per SIMD (workgroups per CU): 3 allow 168 VGPRs, 4 allow 128.  Four spill
+// nothing up to two modes and 20 bytes for three int32 modes with fp64 values (that layout's
+// sort: 984 -> 853 us on the 1e8-nonzero (0,2,1)), but 60-270 bytes elsewhere (four int32
+// modes with fp32 values: 33% slower).
+template <int R, typename CT, typename VT>
+constexpr int small_waves() { return R <= 2 || (R == 3 && sizeof(CT) == 4 && sizeof(VT) == 8) ? 4 : 3; }
 
 // ------------------------------------------------------------------------------ batches
 
