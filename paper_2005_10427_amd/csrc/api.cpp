@@ -31,7 +31,7 @@ struct Layout {
     size_t hist_words = 0;
     size_t status[2] = {};
     size_t status_words = 0;  // per array
-    size_t seg_start = 0, region_seg = 0, bstatus = 0, bstatus_words = 0, geo = 0, seg_hist = 0;
+    size_t seg_start = 0, region_seg = 0, bstatus = 0, bstatus_words = 0, geo = 0, large = 0, seg_hist = 0;
     size_t tile_map = 0;
     size_t pk[2] = {};        // packed-record ping-pong buffers (64-bit words)
     size_t seg_bits = 0;      // segment starts as one bit per record (bucket reuse)
@@ -149,6 +149,8 @@ void make_layout(qsd_plan_s* q) {
         at = up(at + (cdiv(N, kRegion) + 2) * 4);
         L.tile_map = at;
         at = up(at + (size_t)L.max_tiles_large * 16);
+        L.large = at;
+        at = up(at + (size_t)L.max_large * 16);
         L.bstatus_words = cdiv(N, kDiscTile);
         L.bstatus = at;
         at = up(at + L.bstatus_words * 4 * q->nseg_groups);
@@ -582,9 +584,13 @@ qsd_status qsd_transpose(qsd_plan_t plan, int64_t nnz, const void* const* in_crd
         ca.nregions = (n + kRegion - 1) / kRegion;
         ca.large_ctl = large_ctl;
         ca.tile_geo = tile_geo;
+        ca.large = (uint4*)(W + L.large);
         ca.seg_hist = seg_hist;
         ca.hist_stride = (uint32_t)np * kBins;
         QSD_CK(timed(kClassify, 0, stream, [&] { return launch_classify(ca, n, stream); }));
+        QSD_CK(timed(kClassify, 0, stream, [&] {
+            return launch_tile_geo(ca, (uint32_t)std::min<uint64_t>(L.max_tiles_large, (uint64_t)(n + T - 1) / T + n / (kSmallCap + 1) + 1), stream);
+        }));
 
         SmallArgs sa{};
         for (int m = 0; m < p.r; ++m) {

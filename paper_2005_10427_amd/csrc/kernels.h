@@ -194,6 +194,7 @@ struct ClassArgs {
     const uint32_t* region_seg;
     uint32_t nregions;
     uint64_t* large_ctl;
+    uint4* large;               // per large segment: first record, records, first tile
     uint4* tile_geo;            // per large-segment tile: first record, records, the segment's
                                 // first tile, large segment
     uint32_t* seg_hist;         // zeroed per large segment
@@ -245,6 +246,7 @@ hipError_t launch_small_batch(const BatchSmallJob* jobs, uint32_t njobs, int rma
                               int val_bytes, hipStream_t s);
 hipError_t launch_boundary(const BoundArgs& a, int crd_bytes, hipStream_t s);
 hipError_t launch_classify(const ClassArgs& a, uint32_t max_segments, hipStream_t s);
+hipError_t launch_tile_geo(const ClassArgs& a, uint32_t max_tiles, hipStream_t s);
 hipError_t launch_small(const SmallArgs& a, int crd_bytes, int val_bytes, uint32_t max_items,
                         hipStream_t s);
 hipError_t launch_validate(const ValidateArgs& a, int crd_bytes, hipStream_t s);

@@ -93,6 +93,13 @@ hipError_t launch_boundary(const BoundArgs& a, int crd_bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_tile_geo(const ClassArgs& a, uint32_t max_tiles, hipStream_t s) {
+    if (!max_tiles) return hipSuccess;
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((max_tiles + kBlock - 1) / kBlock, (uint32_t)device_cu_count() * 4));
+    hipLaunchKernelGGL(k_tile_geo, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_classify(const ClassArgs& a, uint32_t max_segments, hipStream_t s) {
     const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((max_segments + kBlock - 1) / kBlock, 4096));
     hipLaunchKernelGGL(k_classify, dim3(grid), dim3(kBlock), 0, s, a);

@@ -954,12 +954,32 @@ __global__ void __launch_bounds__(256) k_classify(ClassArgs a) {
             const uint32_t tiles = (len + a.tile - 1) / a.tile;
             const unsigned long long old =
                 atomicAdd((unsigned long long*)a.large_ctl, (1ull << 32) | (unsigned long long)tiles);
-            const uint32_t idx = (uint32_t)(old >> 32), tile_base = (uint32_t)old;
-            for (uint32_t i = 0; i < tiles; ++i)
-                a.tile_geo[tile_base + i] = make_uint4(s + i * a.tile, min(a.tile, len - i * a.tile), tile_base, idx);
+            // segments and their tiles are numbered in the same order: first tiles increase
+            // with the segment number (k_tile_geo searches them)
+            const uint32_t idx = (uint32_t)(old >> 32);
+            a.large[idx] = make_uint4(s, len, (uint32_t)old, 0);
             uint32_t* h = a.seg_hist + (size_t)idx * a.hist_stride;
             for (uint32_t i = 0; i < a.hist_stride; ++i) h[i] = 0;
         }
+    }
+}
+
+// One geometry entry per large-segment tile (first record, records, the segment's first tile,
+// segment), one thread per tile: the tile's segment is the last one whose first tile is at or
+// before it.  Spread over the grid, so that a segment of thousands of tiles costs no single
+// thread thousands of stores.
+__global__ void __launch_bounds__(256) k_tile_geo(ClassArgs a) {
+    const uint64_t ctl = *a.large_ctl;
+    const uint32_t nl = (uint32_t)(ctl >> 32), nt = (uint32_t)ctl;
+    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < nt; t += gridDim.x * kBlock) {
+        uint32_t lo = 0, hi = nl - 1;  // nl >= 1 whenever nt >= 1
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) / 2;
+            if (a.large[mid].z <= t) lo = mid; else hi = mid - 1;
+        }
+        const uint4 g = a.large[lo];
+        const uint32_t i = t - g.z;
+        a.tile_geo[t] = make_uint4(g.x + i * a.tile, min(a.tile, g.y - i * a.tile), g.z, lo);
     }
 }
 
